@@ -1,0 +1,270 @@
+/*
+ * rasp.h -- C ABI of librasp, a GPU hypervisor for word-RASP machines on
+ * AMD MI355X (gfx950).
+ *
+ * The library advances many independent RASP machines in lockstep: the lifted
+ * transition map Phi : C^d -> C^d of Sec. 2 ("Method"), each coordinate being
+ * the one-step transition of the word RASP (Sec. 2.1) or of the classic RASP
+ * (Sec. 1.1).  A machine's configuration is <i, a, M, u, y>: instruction
+ * counter, accumulator, n memory words holding the program and its data,
+ * the input tape (pointer u0 and l words) and the output (count y0 and s
+ * words).  A machine halts when it reaches a fixed point (F = { c : c -> c },
+ * Sec. 1.1 and Sec. 2.1).
+ *
+ * Conventions for every call:
+ *   - the return value is RASP_OK (0) or a negative RASP_E_* code; no C++
+ *     exception crosses this boundary; rasp_last_error() describes the last
+ *     failure on a context;
+ *   - RASP_E_INVAL leaves the context and all batches exactly as they were;
+ *   - RASP_E_DEVICE (a HIP runtime error) is sticky: the context refuses all
+ *     further work except rasp_last_error and rasp_destroy;
+ *   - a context is driven by one host thread at a time;
+ *   - words are 32-bit two's complement (w = 32 of Sec. 3); + and * wrap
+ *     mod 2^32.
+ *
+ * Semantics fixed by this library where the paper leaves a choice:
+ *   - the program is stored in memory: P occupies M[0 .. 2m), n >= 2m words
+ *     in total (Sec. 2: each machine stores its program in memory; Sec. 2.1:
+ *     P in W^(2m <= n), c0 = <0, 0, P 0^(n-2m), x 0^(l-|x|), 0^(s+1)>);
+ *   - memory is addressed circularly by the Euclidean remainder of the signed
+ *     word, M[v mod n] with v mod n in [0, n), for fetch (<M[i mod n],
+ *     M[(i+1) mod n]>, Sec. 2.1) and for data;
+ *   - LOAD is immediate (a <- j) in both instruction sets;
+ *   - READ stores tape word u0 (0-based) into M[j mod n] and increments u0; it
+ *     is a fixed point once u0 >= l (Sec. 2.1 guard);
+ *   - PRINT appends M[j mod n] while y0 < s and is otherwise a no-op that still
+ *     advances i (Sec. 2.1, y :: z);
+ *   - a taken jump is a fixed point exactly when its target word equals i;
+ *   - a retired step is a transition that changes the configuration; a run of
+ *     budget B applies exactly min(B, steps to the fixed point) transitions
+ *     (the halting number tau_h of Sec. 3 when it is below B).
+ */
+#ifndef RASP_H
+#define RASP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RASP_ABI_VERSION 1u
+
+typedef struct rasp_ctx rasp_ctx;
+typedef uint64_t rasp_batch;                 /* 0 is never a valid handle */
+
+enum {
+    RASP_OK = 0,
+    RASP_E_INVAL = -1,     /* bad argument or descriptor; nothing changed   */
+    RASP_E_NOMEM = -2,     /* the context's arena cannot hold the request   */
+    RASP_E_DEVICE = -3,    /* HIP runtime error; sticky for the context     */
+    RASP_E_STATE = -4,     /* unknown or freed handle, wrong call order     */
+    RASP_E_BUSY = -5       /* resource in use by queued work                */
+};
+
+/* Instruction sets.  Both keep the paper's opcode numbers. */
+enum {
+    RASP_ISA_WORD = 0,     /* Sec. 2.1: 1 LOD, 2 ADD, 3 MUL, 4 STO, 5 BNZ (jump if a != 0),
+                              6 RD, 7 PRI; every other value is stuck (halts)          */
+    RASP_ISA_CLASSIC = 1   /* Sec. 1.1: 1 LOAD, 2 ADD, 3 SUB, 4 STORE, 5 JPOS (jump if
+                              a > 0, signed), 6 READ, 7 PRINT; plus 8 JMP (the JMP of
+                              Sec. 2.2 as one instruction); 0 (HALT, the pair 0 0 of
+                              Sec. 2.2) and every other value is stuck                 */
+};
+
+enum { RASP_RUNNING = 0, RASP_HALTED = 1 };
+
+/* rasp_batch_desc.flags */
+enum { RASP_DESC_DEVICE_PTRS = 1u };  /* every array of the descriptor is device memory */
+
+/* rasp_outputs.flags */
+enum { RASP_OUT_DEVICE_PTRS = 1u };   /* every destination is device memory */
+
+/*
+ * rasp_create: open a context on HIP device `device`.
+ *   arena, arena_bytes: device memory the context sub-allocates batches from.
+ *     If arena is NULL the library allocates arena_bytes itself (hipMalloc) and
+ *     frees them in rasp_destroy; otherwise the caller owns the buffer (e.g. a
+ *     torch tensor) and must keep it alive until rasp_destroy returns.
+ *   stream: the hipStream_t all work of this context is queued on (NULL: the
+ *     context creates its own).  The caller keeps a passed stream alive.
+ * Errors: INVAL (out == NULL, arena_bytes < 1 MiB), DEVICE.
+ */
+int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes,
+                void *stream);
+
+/* rasp_destroy: wait for queued work, release the context (NULL is a no-op). */
+int rasp_destroy(rasp_ctx *ctx);
+
+/* rasp_last_error: message for the last failing call on ctx ("" if none).
+ * Valid until the next call on ctx.  ctx may be NULL (message of the last
+ * failed rasp_create). */
+const char *rasp_last_error(const rasp_ctx *ctx);
+
+/*
+ * A batch of machines in packed form.  Machine v (0 <= v < num_vms):
+ *   program words  prog[prog_off[v] .. prog_off[v+1])      (2 m_v words: opcode,
+ *                                                             operand, ...)
+ *   memory size    n_v = mem_words ? mem_words[v] : default_mem_words,
+ *                  1 <= n_v <= 2^30 and n_v >= 2 m_v
+ *   input x_v      tape[tape_off[v] .. tape_off[v+1])
+ *   tape capacity  l_v = tape_cap ? tape_cap[v] : |x_v|, l_v >= |x_v|
+ *   output cap.    s_v = out_cap ? out_cap[v] : default_out_cap
+ * prog_off and tape_off hold num_vms + 1 non-decreasing entries.
+ * With RASP_DESC_DEVICE_PTRS every pointer is device memory on the context's
+ * device; otherwise host memory.  The arrays are only read, and only until the
+ * call that takes the descriptor returns (host) or until the work it queues
+ * has finished on the context stream (device).
+ */
+typedef struct {
+    uint32_t abi_version;            /* RASP_ABI_VERSION */
+    uint32_t isa;                    /* RASP_ISA_* */
+    uint64_t num_vms;                /* >= 1 */
+    const int32_t *prog;
+    const uint64_t *prog_off;
+    const uint32_t *mem_words;       /* NULL: default_mem_words for every machine */
+    uint32_t default_mem_words;
+    uint32_t default_out_cap;
+    const int32_t *tape;
+    const uint64_t *tape_off;
+    const uint32_t *tape_cap;        /* NULL: l_v = |x_v| */
+    const uint32_t *out_cap;         /* NULL: default_out_cap */
+    uint32_t flags;                  /* RASP_DESC_* */
+    uint32_t reserved;
+} rasp_batch_desc;
+
+/*
+ * Per-machine results.  Every pointer may be NULL (that field is not
+ * fetched).  Layouts: the scalar arrays hold num_vms entries; y holds
+ * sum_v s_v words, machine-major (machine v's s_v words after those of
+ * machines 0..v-1), zero beyond y0; mem holds sum_v n_v words, machine-major;
+ * mem_digest holds num_vms FNV-1a-64 hashes of each machine's n_v memory
+ * words taken as little-endian bytes.  Host memory unless flags has
+ * RASP_OUT_DEVICE_PTRS.  For rasp_load_state the same struct carries a state
+ * to load (status is ignored, mem is required, y and steps may be NULL).
+ */
+typedef struct {
+    uint8_t *status;                 /* RASP_RUNNING / RASP_HALTED: is c a fixed point */
+    uint64_t *steps;                 /* transitions retired since load (cumulative) */
+    int32_t *i;
+    int32_t *a;
+    uint32_t *u0;
+    uint32_t *y0;
+    int32_t *y;
+    int32_t *mem;
+    uint64_t *mem_digest;
+    uint32_t flags;                  /* RASP_OUT_* */
+    uint32_t reserved;
+} rasp_outputs;
+
+/*
+ * rasp_batch_footprint: bytes of arena a batch with this descriptor occupies
+ * (state, shapes and the n + l + s words of every machine), for admission
+ * control.  Pure: touches no context.  A device descriptor is read with
+ * synchronous copies on the null stream.
+ * Errors: INVAL (malformed descriptor).
+ */
+int rasp_batch_footprint(const rasp_batch_desc *d, uint64_t *bytes);
+
+/*
+ * rasp_load_batch: allocate a batch in the arena and build c0(P_v, x_v) for
+ * every machine (Sec. 2.1): i = a = 0, M = P 0^(n-2m), tape = x 0^(l-|x|),
+ * u0 = y0 = 0, y = 0^s, steps = 0; status = whether c0 is already a fixed
+ * point.  All or nothing: on error no batch exists.  Queues work on the
+ * context stream and waits only for the descriptor checks.
+ * Errors: INVAL (descriptor), NOMEM (arena), DEVICE.
+ */
+int rasp_load_batch(rasp_ctx *ctx, const rasp_batch_desc *d, rasp_batch *out);
+
+/*
+ * rasp_load_state: like rasp_load_batch (the descriptor gives shapes, tapes and
+ * the isa; its program words are ignored beyond validation), then overwrite
+ * every machine's i, a, u0, y0, steps, y and memory from `state` (host or
+ * device per state->flags).  status is recomputed.  u0 <= l and y0 <= s are
+ * required.  Used to resume from a checkpoint and to test arbitrary states.
+ * Errors: INVAL, NOMEM, DEVICE.
+ */
+int rasp_load_state(rasp_ctx *ctx, const rasp_batch_desc *d, const rasp_outputs *state,
+                    rasp_batch *out);
+
+/*
+ * rasp_run: queue the advance of every machine of batch b by at most `budget`
+ * more transitions (Phi^budget, Sec. 2).  Runs compose: run(b1) then run(b2)
+ * equals run(b1 + b2).  Halted machines never change.  Returns once the work
+ * is queued; use rasp_sync / rasp_fetch_outputs to wait.
+ * Errors: STATE (bad handle), DEVICE.
+ */
+int rasp_run(rasp_ctx *ctx, rasp_batch b, uint64_t budget);
+
+/*
+ * rasp_run_multi: one persistent launch that advances k batches together,
+ * batch bs[t] by at most budgets[t] transitions (continuous batching: machines
+ * of every batch share the device work queue).  k <= 64.  Equivalent to
+ * rasp_run on each batch in turn.
+ * Errors: INVAL (k), STATE, DEVICE.
+ */
+int rasp_run_multi(rasp_ctx *ctx, const rasp_batch *bs, const uint64_t *budgets, uint32_t k);
+
+/* rasp_poll: *done = 1 when all work queued so far on ctx has finished. */
+int rasp_poll(rasp_ctx *ctx, int *done);
+
+/* rasp_sync: wait for all work queued on ctx. */
+int rasp_sync(rasp_ctx *ctx);
+
+/*
+ * rasp_fetch_outputs: wait for the batch's queued work, then copy the requested
+ * fields into caller-owned buffers (layouts above).
+ * Errors: STATE, DEVICE.
+ */
+int rasp_fetch_outputs(rasp_ctx *ctx, rasp_batch b, const rasp_outputs *out);
+
+/*
+ * rasp_batch_info: num_vms, total memory words, total output words and the
+ * retired-step sum of a batch (the sum needs a device reduction and a wait;
+ * pass NULL to skip it).
+ */
+int rasp_batch_info(rasp_ctx *ctx, rasp_batch b, uint64_t *num_vms, uint64_t *mem_words,
+                    uint64_t *out_words, uint64_t *steps_sum);
+
+/* rasp_free_batch: release a batch's arena space after its queued work. */
+int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
+
+/*
+ * Scheduling knobs (per context).  The library's autotuner sets them; they can
+ * also be forced.
+ *   RASP_OPT_SCHEDULE      RASP_SCHED_PLAIN: one machine per lane, every lane
+ *                          runs its machine to the end, no compaction;
+ *                          RASP_SCHED_PERSISTENT: resident waves refill lanes
+ *                          of halted machines from a device queue;
+ *                          RASP_SCHED_AUTO (default): the autotuned choice.
+ *   RASP_OPT_EPOCH         steps a lane runs between refill checks (q), >= 1
+ *   RASP_OPT_LDS_WORDS     memory words per machine staged in LDS by the
+ *                          persistent kernel (0 = none), power of two <= 1024
+ *   RASP_OPT_WAVES_PER_CU  resident waves per compute unit for the persistent
+ *                          kernel
+ *   RASP_OPT_GRAPH         1: replay persistent launches through a HIP graph
+ *   RASP_OPT_FIRST_PASS    persistent schedule only: transitions every machine
+ *                          first runs in a plain one-machine-per-lane pass;
+ *                          the machines still running then go through the
+ *                          persistent kernel (0: persistent kernel only)
+ */
+enum {
+    RASP_OPT_SCHEDULE = 1,
+    RASP_OPT_EPOCH = 2,
+    RASP_OPT_LDS_WORDS = 3,
+    RASP_OPT_WAVES_PER_CU = 4,
+    RASP_OPT_GRAPH = 5,
+    RASP_OPT_FIRST_PASS = 6
+};
+enum { RASP_SCHED_AUTO = 0, RASP_SCHED_PLAIN = 1, RASP_SCHED_PERSISTENT = 2 };
+
+int rasp_set_option(rasp_ctx *ctx, int option, int64_t value);
+int rasp_get_option(rasp_ctx *ctx, int option, int64_t *value);
+
+/* Device properties the context saw: compute units, LDS bytes per workgroup. */
+int rasp_device_info(rasp_ctx *ctx, int *compute_units, int *lds_bytes, int *wave_size);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RASP_H */

@@ -1,0 +1,102 @@
+// rasp_internal.h -- structures shared by the host runtime and the kernels of
+// librasp (never exposed through the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rasp {
+
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kMaxMulti = 64;          // batches per multi-batch launch
+constexpr uint32_t kMaxMemWords = 1u << 30;
+
+// Device view of one batch: struct-of-arrays machine state plus the packed
+// per-machine shapes and the three word arenas (memory, tape, output), each
+// machine's slice contiguous.  Memory slices start on 16-byte boundaries.
+struct DevBatch {
+    int32_t *i;
+    int32_t *a;
+    uint32_t *u0;
+    uint32_t *y0;
+    uint64_t *steps;
+    uint8_t *status;
+    uint32_t *n;
+    uint32_t *ell;
+    uint32_t *s;
+    uint64_t *mem_off;                 // word offset of M_v in M
+    uint64_t *t_off;                   // word offset of tape_v in T
+    uint64_t *y_off;                   // word offset of y_v in Y
+    int32_t *M;
+    int32_t *T;
+    int32_t *Y;
+    uint64_t N;
+    uint32_t isa;
+    uint32_t pad;
+};
+
+// Table of batches advanced together by one launch.  Machine g of the launch
+// is machine g - start[k] of batch k, for the k with start[k] <= g < start[k+1].
+struct BatchTable {
+    DevBatch b[kMaxMulti];
+    uint64_t start[kMaxMulti + 1];
+    uint32_t budget[kMaxMulti];        // transitions this launch may apply per machine
+    uint32_t count;
+    uint32_t pad;
+};
+
+// Counters of one persistent launch (device memory, zeroed by a fill kernel
+// before every launch so that the launch can sit in a HIP graph).
+struct QueueState {
+    unsigned long long head;           // next unclaimed work item
+    unsigned long long survivors;      // items appended to the survivor list
+    unsigned long long retired;        // transitions retired (statistics)
+    unsigned long long pad;
+};
+
+// Descriptor-check error bits.
+enum : uint32_t {
+    kErrOffsets = 1u,                  // prog_off / tape_off decreasing
+    kErrProgTooLong = 2u,              // 2m > n
+    kErrTapeTooLong = 4u,              // |x| > l
+    kErrMemSize = 8u,                  // n == 0 or n > 2^30
+    kErrStateRange = 16u               // u0 > l or y0 > s in a loaded state
+};
+
+struct LaunchShape {
+    int cus;
+    int lds_bytes;
+};
+
+// kernel launchers (rasp_kernels.hip)
+hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
+                         const uint32_t *mem_words, uint32_t def_mem,
+                         const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
+                         uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
+                         uint64_t *n_pad, uint32_t *err, hipStream_t st);
+hipError_t launch_scan_u64(const uint64_t *in, uint64_t *out_excl, uint64_t N,
+                           uint64_t *block_sums, uint64_t *total, hipStream_t st);
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out_excl, uint64_t N,
+                           uint64_t *block_sums, uint64_t *total, hipStream_t st);
+uint64_t scan_scratch_words(uint64_t N);
+hipError_t launch_pack(DevBatch b, const int32_t *prog, const uint64_t *prog_off,
+                       const int32_t *tape, const uint64_t *tape_off, hipStream_t st);
+hipError_t launch_check_state(DevBatch b, uint32_t *err, hipStream_t st);
+hipError_t launch_probe(DevBatch b, hipStream_t st);
+hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap,
+                        uint32_t isa, uint32_t *surv, QueueState *q, hipStream_t st);
+hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
+                             uint32_t already, uint32_t isa, uint32_t epoch, uint32_t lds_words,
+                             uint32_t waves_per_block, uint32_t blocks,
+                             QueueState *q, hipStream_t st);
+hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
+hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st);
+hipError_t launch_steps_sum(DevBatch b, unsigned long long *out, hipStream_t st);
+hipError_t launch_gather_words(const int32_t *src, const uint64_t *off, const uint32_t *len,
+                               uint64_t N, int32_t *dst, const uint64_t *dst_off,
+                               hipStream_t st);
+hipError_t launch_scatter_words(const int32_t *src, const uint64_t *src_off,
+                                const uint32_t *len, uint64_t N, int32_t *dst,
+                                const uint64_t *dst_off, hipStream_t st);
+
+}  // namespace rasp

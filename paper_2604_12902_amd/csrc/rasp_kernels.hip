@@ -1,0 +1,755 @@
+// rasp_kernels.hip -- gfx950 kernels of librasp.
+//
+// The step loop advances one RASP machine per lane.  A machine's configuration
+// <i, a, M, u, y> (Sec. 1.1; word RASP of Sec. 2.1) lives in struct-of-arrays
+// scalars (i, a, u0, y0, steps, status) plus per-machine word slices of three
+// arenas: memory M (program stored at M[0..2m), Sec. 2), tape T, output Y.
+//
+// One transition (Sec. 2.1 case table; classic set of Sec. 1.1 plus JMP):
+//   fetch   o = M[i mod n], j = M[(i+1) mod n]      (circular addressing)
+//   decode  one-hot choice of the case (the guarded sum of Sec. 2.1, taken as
+//           predicates rather than branches); the machine is at a fixed point
+//           (F) when no case moves it: unknown opcode, READ with u0 >= l, or a
+//           taken jump whose target equals i
+//   execute LOAD a <- j; ADD/SUB/MUL a <- a (+,-,*) M[j mod n]; STORE
+//           M[j mod n] <- a; READ M[j mod n] <- T[u0], u0++; PRINT (if y0 < s)
+//           Y[y0] <- M[j mod n], y0++; jumps i <- j; otherwise i <- i + 2;
+//           all word arithmetic wraps mod 2^32.
+// `mod n` is the Euclidean remainder of the signed word (result in [0, n)).
+// The position p = i mod n is carried along with i so that the usual
+// sequential advance costs an add and a compare instead of a division.
+
+#include "rasp_internal.h"
+
+namespace rasp {
+
+// ---------------------------------------------------------------------------
+// circular addressing
+// ---------------------------------------------------------------------------
+
+__device__ __noinline__ uint32_t cmod_slow(int32_t v, uint32_t n)
+{
+    const int32_t r = v % static_cast<int32_t>(n);          // n <= 2^30
+    return static_cast<uint32_t>(r < 0 ? r + static_cast<int32_t>(n) : r);
+}
+
+__device__ __forceinline__ uint32_t cmod(int32_t v, uint32_t n)
+{
+    return (static_cast<uint32_t>(v) < n) ? static_cast<uint32_t>(v) : cmod_slow(v, n);
+}
+
+// position of the operand word (i + 1) mod n, given p = i mod n
+__device__ __forceinline__ uint32_t operand_pos(int32_t i, uint32_t p, uint32_t n)
+{
+    if (i == INT32_MAX) return cmod(INT32_MIN, n);          // i + 1 wraps
+    const uint32_t q = p + 1u;
+    return q == n ? 0u : q;
+}
+
+// position of i + 2 (wrapping) given p = i mod n
+__device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t n)
+{
+    if (i > INT32_MAX - 2)
+        return cmod(static_cast<int32_t>(static_cast<uint32_t>(i) + 2u), n);
+    uint32_t q = p + 2u;
+    if (q >= n) q -= n;
+    if (q >= n) q -= n;                                     // n == 1
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// memory accessors
+// ---------------------------------------------------------------------------
+
+struct GlobalMem {                       // every word in HBM
+    int32_t *M;
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v) const { M[k] = v; }
+};
+
+struct StagedMem {                       // words [0, P) in the lane's LDS slot
+    int32_t *L;
+    int32_t *M;
+    uint32_t P;
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return k < P ? L[k] : M[k]; }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v) const
+    {
+        if (k < P) L[k] = v; else M[k] = v;
+    }
+};
+
+struct C0Mem {                           // c0 read straight from the packed program
+    const int32_t *P;
+    uint32_t plen;
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return k < plen ? P[k] : 0; }
+    __device__ __forceinline__ void st(uint32_t, int32_t) const {}
+};
+
+// ---------------------------------------------------------------------------
+// the step loop
+// ---------------------------------------------------------------------------
+
+struct Regs {
+    int32_t i, a;
+    uint32_t p;          // i mod n
+    uint32_t u0, y0;
+    uint32_t n, ell, s;
+};
+
+// Advance one machine by at most `limit` transitions.  Returns the number
+// applied; `halted` says whether the machine now sits on a fixed point.
+template <int ISA, class Mem>
+__device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
+                                                const int32_t *__restrict__ T,
+                                                int32_t *__restrict__ Y,
+                                                uint32_t limit, bool &halted)
+{
+    uint32_t t = 0;
+    halted = false;
+    for (;;) {
+        const int32_t o = mem.ld(r.p);
+        const int32_t j = mem.ld(operand_pos(r.i, r.p, r.n));
+        const uint32_t op = static_cast<uint32_t>(o);
+
+        bool is_ld, is_add, is_sub, is_mul, is_sto, is_rd, is_pr, taken, valid;
+        is_ld = op == 1u;
+        is_add = op == 2u;
+        is_sto = op == 4u;
+        is_rd = op == 6u;
+        is_pr = op == 7u;
+        if (ISA == 1) {                  // classic: SUB, JPOS (a > 0), JMP
+            is_sub = op == 3u;
+            is_mul = false;
+            taken = (op == 8u) | ((op == 5u) & (r.a > 0));
+            valid = (op - 1u) < 8u;
+        } else {                         // word: MUL, BNZ (a != 0)
+            is_sub = false;
+            is_mul = op == 3u;
+            taken = (op == 5u) & (r.a != 0);
+            valid = (op - 1u) < 7u;
+        }
+        const bool rd_ok = is_rd & (r.u0 < r.ell);
+        const bool fixed = !valid | (is_rd & !rd_ok) | (taken & (j == r.i));
+        if (fixed) { halted = true; break; }
+        if (t == limit) break;
+
+        const uint32_t jj = cmod(j, r.n);
+        int32_t d = 0;
+        if (is_add | is_sub | is_mul | is_pr) d = mem.ld(jj);
+        if (is_sto) mem.st(jj, r.a);
+        if (rd_ok) { mem.st(jj, T[r.u0]); r.u0 += 1u; }
+        if (is_pr & (r.y0 < r.s)) { Y[r.y0] = d; r.y0 += 1u; }
+        const uint32_t ua = static_cast<uint32_t>(r.a), ud = static_cast<uint32_t>(d);
+        uint32_t na = ua;
+        if (is_ld) na = static_cast<uint32_t>(j);
+        if (is_add) na = ua + ud;
+        if (is_sub) na = ua - ud;
+        if (is_mul) na = ua * ud;
+        r.a = static_cast<int32_t>(na);
+        if (taken) {
+            r.i = j;
+            r.p = jj;
+        } else {
+            r.p = advance_pos(r.i, r.p, r.n);
+            r.i = static_cast<int32_t>(static_cast<uint32_t>(r.i) + 2u);
+        }
+        ++t;
+    }
+    return t;
+}
+
+__device__ __forceinline__ int batch_of(const BatchTable *tab, uint64_t g)
+{
+    int lo = 0, hi = static_cast<int>(tab->count) - 1;
+    while (lo < hi) {                    // last k with start[k] <= g
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab->start[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// K1: pack c0 (Sec. 2.1): M = P 0^(n-2m), T = x 0^(l-|x|), Y = 0^s, scalars 0
+// One wave per machine, grid-stride; status = is c0 a fixed point.
+// ---------------------------------------------------------------------------
+
+template <int ISA>
+__global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restrict__ prog,
+                                              const uint64_t *__restrict__ prog_off,
+                                              const int32_t *__restrict__ tape,
+                                              const uint64_t *__restrict__ tape_off)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t v = wave; v < b.N; v += nwaves) {
+        const uint64_t p0 = prog_off[v];
+        const uint32_t plen = static_cast<uint32_t>(prog_off[v + 1] - p0);
+        const uint64_t t0 = tape_off[v];
+        const uint32_t tlen = static_cast<uint32_t>(tape_off[v + 1] - t0);
+        const uint32_t n = b.n[v], ell = b.ell[v], s = b.s[v];
+        int32_t *M = b.M + b.mem_off[v];
+        int32_t *T = b.T + b.t_off[v];
+        int32_t *Y = b.Y + b.y_off[v];
+        for (uint32_t k = lane; k < n; k += kWave) M[k] = k < plen ? prog[p0 + k] : 0;
+        for (uint32_t k = lane; k < ell; k += kWave) T[k] = k < tlen ? tape[t0 + k] : 0;
+        for (uint32_t k = lane; k < s; k += kWave) Y[k] = 0;
+        if (lane == 0) {
+            Regs r{0, 0, 0, 0, 0, n, ell, s};
+            C0Mem c0{prog + p0, plen};
+            bool halted;
+            run_machine<ISA>(c0, r, T, Y, 0u, halted);
+            b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0;
+            b.status[v] = halted ? 1 : 0;
+        }
+    }
+}
+
+hipError_t launch_pack(DevBatch b, const int32_t *prog, const uint64_t *prog_off,
+                       const int32_t *tape, const uint64_t *tape_off, hipStream_t st)
+{
+    const uint64_t waves = b.N;
+    uint64_t blocks = (waves + 3) / 4;
+    if (blocks > 65536 * 4) blocks = 65536 * 4;
+    if (b.isa == 1)
+        k_pack<1><<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st>>>(b, prog, prog_off, tape, tape_off);
+    else
+        k_pack<0><<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st>>>(b, prog, prog_off, tape, tape_off);
+    return hipGetLastError();
+}
+
+// status of every machine = is its current configuration a fixed point
+template <int ISA>
+__global__ __launch_bounds__(256) void k_probe(DevBatch b)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= b.N) return;
+    Regs r;
+    r.n = b.n[v]; r.ell = b.ell[v]; r.s = b.s[v];
+    r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
+    r.p = cmod(r.i, r.n);
+    GlobalMem g{b.M + b.mem_off[v]};
+    bool halted;
+    run_machine<ISA>(g, r, b.T + b.t_off[v], b.Y + b.y_off[v], 0u, halted);
+    b.status[v] = halted ? 1 : 0;
+}
+
+hipError_t launch_probe(DevBatch b, hipStream_t st)
+{
+    const unsigned blocks = static_cast<unsigned>((b.N + 255) / 256);
+    if (b.isa == 1) k_probe<1><<<blocks, 256, 0, st>>>(b);
+    else k_probe<0><<<blocks, 256, 0, st>>>(b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K2: plain step loop, one machine per lane, memory in HBM, no compaction.
+// Every lane runs its machine for at most `cap` transitions.  With cap below
+// the batch budget, machines still running are appended (wave-aggregated
+// atomic) to the survivor list for the persistent kernel.
+// ---------------------------------------------------------------------------
+
+template <int ISA>
+__global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ tab, uint64_t total,
+                                               uint32_t cap, uint32_t *__restrict__ surv,
+                                               QueueState *__restrict__ q)
+{
+    const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool survive = false;
+    unsigned long long retired = 0;
+    if (g < total) {
+        const int k = batch_of(tab, g);
+        const DevBatch &b = tab->b[k];
+        const uint64_t v = g - tab->start[k];
+        const uint32_t budget = tab->budget[k];
+        if (b.status[v] == 0 && budget > 0) {
+            Regs r;
+            r.n = b.n[v]; r.ell = b.ell[v]; r.s = b.s[v];
+            r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
+            r.p = cmod(r.i, r.n);
+            const uint32_t limit = cap < budget ? cap : budget;
+            GlobalMem m{b.M + b.mem_off[v]};
+            bool halted;
+            const uint32_t t = run_machine<ISA>(m, r, b.T + b.t_off[v], b.Y + b.y_off[v], limit, halted);
+            b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
+            b.steps[v] += t;
+            b.status[v] = halted ? 1 : 0;
+            retired = t;
+            survive = !halted && t == limit && limit < budget;
+        }
+    }
+    if (surv != nullptr) {
+        const uint64_t mask = __ballot(survive);
+        if (mask) {
+            const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+            const uint32_t lane = threadIdx.x & (kWave - 1);
+            unsigned long long base = 0;
+            if (lane == static_cast<uint32_t>(leader))
+                base = atomicAdd(&q->survivors, static_cast<unsigned long long>(__popcll(mask)));
+            base = __shfl(base, leader);
+            if (survive) {
+                const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
+                surv[base + rank] = static_cast<uint32_t>(g);
+            }
+        }
+    }
+    (void)retired;
+}
+
+hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uint32_t isa,
+                        uint32_t *surv, QueueState *q, hipStream_t st)
+{
+    const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    if (isa == 1) k_plain<1><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+    else k_plain<0><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K3: persistent step loop.  Resident waves pull work items from a device
+// queue (one agent-scope atomic per wave refill), run each lane's machine for
+// at most `epoch` transitions between refill points, write back machines
+// that halted or spent their budget, and refill exactly those lanes (wave
+// ballot + popcount prefix ranks).  Memory words [0, P) of each live machine
+// are staged in the lane's LDS slot (P = lds_words; 0 keeps everything in
+// HBM); staging and write-back are cooperative 64-lane copies.
+// Work item k is machine work[k] of the launch (or machine k when work is
+// null); machines have already applied `already` transitions this run.
+// ---------------------------------------------------------------------------
+
+template <int ISA, bool STAGED>
+__global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict__ tab,
+                                                    uint64_t total,
+                                                    const uint32_t *__restrict__ work,
+                                                    uint32_t already, uint32_t epoch,
+                                                    uint32_t P, QueueState *__restrict__ q)
+{
+    extern __shared__ int32_t lds[];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wib = threadIdx.x / kWave;
+    if (work != nullptr) total = q->survivors;           // written by the plain pass
+    int32_t *slot = STAGED ? lds + static_cast<size_t>(wib * kWave + lane) * P : nullptr;
+
+    bool has = false;
+    bool exhausted = false;
+    Regs r{};
+    int32_t *M = nullptr;
+    const int32_t *T = nullptr;
+    int32_t *Y = nullptr;
+    uint32_t done = 0, limit = 0;
+    const DevBatch *bp = nullptr;
+    uint64_t v = 0;
+    bool dirty = false;
+
+    for (;;) {
+        // ---- refill idle lanes from the queue ----
+        const uint64_t idle = __ballot(!has);
+        uint64_t fresh_mask = 0;
+        if (idle != 0 && !exhausted) {
+            const int leader = __ffsll(static_cast<unsigned long long>(idle)) - 1;
+            const uint32_t cnt = __popcll(idle);
+            unsigned long long base = 0;
+            if (lane == static_cast<uint32_t>(leader))
+                base = __hip_atomic_fetch_add(&q->head, static_cast<unsigned long long>(cnt),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            base = __shfl(base, leader);
+            if (base + cnt >= total) exhausted = true;
+            bool fresh = false;
+            if (!has) {
+                const uint64_t item = base + __popcll(idle & ((1ull << lane) - 1ull));
+                if (item < total) {
+                    const uint64_t g = work ? static_cast<uint64_t>(work[item]) : item;
+                    const int k = batch_of(tab, g);
+                    bp = &tab->b[k];
+                    v = g - tab->start[k];
+                    const uint32_t budget = tab->budget[k];
+                    if (bp->status[v] == 0 && budget > already) {
+                        r.n = bp->n[v]; r.ell = bp->ell[v]; r.s = bp->s[v];
+                        r.i = bp->i[v]; r.a = bp->a[v]; r.u0 = bp->u0[v]; r.y0 = bp->y0[v];
+                        r.p = cmod(r.i, r.n);
+                        M = bp->M + bp->mem_off[v];
+                        T = bp->T + bp->t_off[v];
+                        Y = bp->Y + bp->y_off[v];
+                        done = 0;
+                        limit = budget - already;
+                        dirty = false;
+                        has = true;
+                        fresh = true;
+                    }
+                }
+            }
+            fresh_mask = __ballot(fresh);
+        }
+        if (__ballot(has) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        // ---- stage the fresh machines' low memory words into LDS ----
+        if (STAGED && fresh_mask) {
+            uint64_t m = fresh_mask;
+            while (m) {
+                const int L = __ffsll(static_cast<unsigned long long>(m)) - 1;
+                m &= m - 1;
+                const uint64_t mp = reinterpret_cast<uint64_t>(M);
+                const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp), L);
+                const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp >> 32), L);
+                const uint32_t nL = __builtin_amdgcn_readlane(r.n, L);
+                const int32_t *src = reinterpret_cast<const int32_t *>((static_cast<uint64_t>(hi) << 32) | lo);
+                int32_t *dst = lds + static_cast<size_t>(wib * kWave + L) * P;
+                const uint32_t cnt = nL < P ? nL : P;
+                for (uint32_t k = lane; k < cnt; k += kWave) dst[k] = src[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // ---- run ----
+        bool finish = false;
+        if (has) {
+            uint32_t lim = limit - done;
+            if (lim > epoch) lim = epoch;
+            bool halted;
+            uint32_t t;
+            if (STAGED) {
+                StagedMem sm{slot, M, P};
+                t = run_machine<ISA>(sm, r, T, Y, lim, halted);
+                // conservatively dirty once anything ran: a store may have hit LDS
+                dirty |= (t != 0);
+            } else {
+                GlobalMem gm{M};
+                t = run_machine<ISA>(gm, r, T, Y, lim, halted);
+            }
+            done += t;
+            if (halted || done == limit) {
+                bp->i[v] = r.i; bp->a[v] = r.a; bp->u0[v] = r.u0; bp->y0[v] = r.y0;
+                bp->steps[v] += done;
+                bp->status[v] = halted ? 1 : 0;
+                finish = true;
+            }
+        }
+        // ---- write back staged words of finished machines ----
+        if (STAGED) {
+            uint64_t m = __ballot(finish && dirty);
+            if (m) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            while (m) {
+                const int L = __ffsll(static_cast<unsigned long long>(m)) - 1;
+                m &= m - 1;
+                const uint64_t mp = reinterpret_cast<uint64_t>(M);
+                const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp), L);
+                const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp >> 32), L);
+                const uint32_t nL = __builtin_amdgcn_readlane(r.n, L);
+                int32_t *dst = reinterpret_cast<int32_t *>((static_cast<uint64_t>(hi) << 32) | lo);
+                const int32_t *src = lds + static_cast<size_t>(wib * kWave + L) * P;
+                const uint32_t cnt = nL < P ? nL : P;
+                for (uint32_t k = lane; k < cnt; k += kWave) dst[k] = src[k];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (finish) has = false;
+    }
+}
+
+hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
+                                uint32_t already, uint32_t isa, uint32_t epoch,
+                                uint32_t lds_words, uint32_t waves_per_block, uint32_t blocks,
+                                QueueState *q, hipStream_t st)
+{
+    const dim3 grid(blocks), block(waves_per_block * kWave);
+    const size_t shmem = static_cast<size_t>(waves_per_block) * kWave * lds_words * sizeof(int32_t);
+    if (lds_words > 0) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<1, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<0, true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            (void)hipGetLastError();
+            attr_set = true;
+        }
+        if (isa == 1)
+            k_persistent<1, true><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
+        else
+            k_persistent<0, true><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
+    } else {
+        if (isa == 1)
+            k_persistent<1, false><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
+        else
+            k_persistent<0, false><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
+    }
+    return hipGetLastError();
+}
+
+__global__ void k_zero_queue(QueueState *q)
+{
+    if (threadIdx.x == 0) { q->head = 0; q->survivors = 0; q->retired = 0; q->pad = 0; }
+}
+
+hipError_t launch_zero_queue(QueueState *q, hipStream_t st)
+{
+    k_zero_queue<<<1, 64, 0, st>>>(q);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// K4: FNV-1a-64 digest of each machine's memory (little-endian bytes),
+// one lane per machine, 16-byte loads (memory slices are 16-byte aligned).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_digest(DevBatch b, uint64_t *__restrict__ out)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= b.N) return;
+    const uint32_t n = b.n[v];
+    const int32_t *M = b.M + b.mem_off[v];
+    uint64_t h = 0xcbf29ce484222325ull;
+    const uint64_t prime = 0x100000001b3ull;
+    uint32_t k = 0;
+    for (; k + 4 <= n; k += 4) {
+        const int4 w = *reinterpret_cast<const int4 *>(M + k);
+        const uint32_t ws[4] = {static_cast<uint32_t>(w.x), static_cast<uint32_t>(w.y),
+                                static_cast<uint32_t>(w.z), static_cast<uint32_t>(w.w)};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int byte = 0; byte < 4; ++byte) { h ^= (ws[e] >> (8 * byte)) & 0xffu; h *= prime; }
+    }
+    for (; k < n; ++k) {
+        const uint32_t x = static_cast<uint32_t>(M[k]);
+#pragma unroll
+        for (int byte = 0; byte < 4; ++byte) { h ^= (x >> (8 * byte)) & 0xffu; h *= prime; }
+    }
+    out[v] = h;
+}
+
+hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st)
+{
+    k_digest<<<static_cast<unsigned>((b.N + 255) / 256), 256, 0, st>>>(b, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_steps_sum(DevBatch b, unsigned long long *out)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    unsigned long long x = v < b.N ? b.steps[v] : 0ull;
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off);
+    if ((threadIdx.x & (kWave - 1)) == 0 && x) atomicAdd(out, x);
+}
+
+hipError_t launch_steps_sum(DevBatch b, unsigned long long *out, hipStream_t st)
+{
+    k_steps_sum<<<static_cast<unsigned>((b.N + 255) / 256), 256, 0, st>>>(b, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// descriptor checks and shapes
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_shapes(const uint64_t *__restrict__ prog_off,
+                                                const uint64_t *__restrict__ tape_off,
+                                                const uint32_t *__restrict__ mem_words, uint32_t def_mem,
+                                                const uint32_t *__restrict__ tape_cap,
+                                                const uint32_t *__restrict__ out_cap, uint32_t def_out,
+                                                uint64_t N, uint32_t *__restrict__ n_out,
+                                                uint32_t *__restrict__ ell_out, uint32_t *__restrict__ s_out,
+                                                uint64_t *__restrict__ n_pad, uint32_t *__restrict__ err)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    uint32_t e = 0;
+    const uint64_t p0 = prog_off[v], p1 = prog_off[v + 1];
+    const uint64_t t0 = tape_off[v], t1 = tape_off[v + 1];
+    if (p1 < p0 || t1 < t0) e |= kErrOffsets;
+    const uint64_t plen = p1 >= p0 ? p1 - p0 : 0;
+    const uint64_t tlen = t1 >= t0 ? t1 - t0 : 0;
+    const uint32_t n = mem_words ? mem_words[v] : def_mem;
+    const uint64_t ell = tape_cap ? static_cast<uint64_t>(tape_cap[v]) : tlen;
+    const uint32_t s = out_cap ? out_cap[v] : def_out;
+    if (n == 0 || n > kMaxMemWords) e |= kErrMemSize;
+    if (plen > n) e |= kErrProgTooLong;
+    if (tlen > ell || ell > 0x7fffffffull) e |= kErrTapeTooLong;
+    if (s > 0x7fffffffu) e |= kErrMemSize;
+    n_out[v] = n;
+    ell_out[v] = static_cast<uint32_t>(ell);
+    s_out[v] = s;
+    n_pad[v] = (static_cast<uint64_t>(n) + 3ull) & ~3ull;
+    if (e) atomicOr(err, e);
+}
+
+hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
+                         const uint32_t *mem_words, uint32_t def_mem,
+                         const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
+                         uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
+                         uint64_t *n_pad, uint32_t *err, hipStream_t st)
+{
+    k_shapes<<<static_cast<unsigned>((N + 255) / 256), 256, 0, st>>>(
+        prog_off, tape_off, mem_words, def_mem, tape_cap, out_cap, def_out, N, n, ell, s, n_pad, err);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_check_state(DevBatch b, uint32_t *err)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= b.N) return;
+    if (b.u0[v] > b.ell[v] || b.y0[v] > b.s[v]) atomicOr(err, kErrStateRange);
+}
+
+hipError_t launch_check_state(DevBatch b, uint32_t *err, hipStream_t st)
+{
+    k_check_state<<<static_cast<unsigned>((b.N + 255) / 256), 256, 0, st>>>(b, err);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan (u32 or u64 in, u64 out): 1024 items per block
+// ---------------------------------------------------------------------------
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr uint64_t kScanTile = kScanBlock * kScanItems;
+
+uint64_t scan_scratch_words(uint64_t N) { return (N + kScanTile - 1) / kScanTile + 1; }
+
+template <class T>
+__device__ __forceinline__ uint64_t block_exclusive(uint64_t x, uint64_t *tmp, uint64_t &total)
+{
+    // inclusive scan inside each wave, then across the block's waves
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint64_t incl = x;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t y = __shfl_up(incl, off);
+        if (lane >= static_cast<uint32_t>(off)) incl += y;
+    }
+    if (lane == kWave - 1) tmp[w] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    total = 0;
+    for (int k = 0; k < kScanBlock / kWave; ++k) {
+        if (k < static_cast<int>(w)) before += tmp[k];
+        total += tmp[k];
+    }
+    __syncthreads();
+    return before + incl - x;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const T *__restrict__ in, uint64_t N,
+                                                           uint64_t *__restrict__ sums)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    const uint64_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint64_t x = 0;
+    for (int e = 0; e < kScanItems; ++e)
+        if (base + e < N) x += static_cast<uint64_t>(in[base + e]);
+    uint64_t total;
+    block_exclusive<T>(x, tmp, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(uint64_t *sums, uint64_t nb, uint64_t *total_out)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < nb; b0 += kScanBlock) {
+        const uint64_t idx = b0 + threadIdx.x;
+        const uint64_t x = idx < nb ? sums[idx] : 0;
+        uint64_t total;
+        const uint64_t ex = block_exclusive<uint64_t>(x, tmp, total);
+        if (idx < nb) sums[idx] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *total_out = carry;
+}
+
+template <class T>
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const T *__restrict__ in, uint64_t N,
+                                                           const uint64_t *__restrict__ sums,
+                                                           uint64_t *__restrict__ out)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    const uint64_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint64_t vals[kScanItems];
+    uint64_t x = 0;
+    for (int e = 0; e < kScanItems; ++e) {
+        vals[e] = base + e < N ? static_cast<uint64_t>(in[base + e]) : 0;
+        x += vals[e];
+    }
+    uint64_t total;
+    uint64_t run = sums[blockIdx.x] + block_exclusive<T>(x, tmp, total);
+    for (int e = 0; e < kScanItems; ++e) {
+        if (base + e < N) out[base + e] = run;
+        run += vals[e];
+    }
+}
+
+template <class T>
+static hipError_t scan_impl(const T *in, uint64_t *out, uint64_t N, uint64_t *sums,
+                            uint64_t *total, hipStream_t st)
+{
+    const uint64_t nb = (N + kScanTile - 1) / kScanTile;
+    if (nb == 0) return hipSuccess;
+    k_scan_tiles<T><<<static_cast<unsigned>(nb), kScanBlock, 0, st>>>(in, N, sums);
+    k_scan_sums<<<1, kScanBlock, 0, st>>>(sums, nb, total);
+    k_scan_apply<T><<<static_cast<unsigned>(nb), kScanBlock, 0, st>>>(in, N, sums, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u64(const uint64_t *in, uint64_t *out, uint64_t N, uint64_t *sums,
+                           uint64_t *total, hipStream_t st)
+{
+    return scan_impl<uint64_t>(in, out, N, sums, total, st);
+}
+
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t N, uint64_t *sums,
+                           uint64_t *total, hipStream_t st)
+{
+    return scan_impl<uint32_t>(in, out, N, sums, total, st);
+}
+
+// ---------------------------------------------------------------------------
+// ragged copies between the padded memory arena and dense machine-major arrays
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_copy_ragged(const int32_t *__restrict__ src,
+                                                     const uint64_t *__restrict__ src_off,
+                                                     const uint32_t *__restrict__ len, uint64_t N,
+                                                     int32_t *__restrict__ dst,
+                                                     const uint64_t *__restrict__ dst_off)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
+    for (uint64_t v = wave; v < N; v += nwaves) {
+        const uint32_t n = len[v];
+        const int32_t *s = src + src_off[v];
+        int32_t *d = dst + dst_off[v];
+        for (uint32_t k = lane; k < n; k += kWave) d[k] = s[k];
+    }
+}
+
+static hipError_t copy_ragged(const int32_t *src, const uint64_t *src_off, const uint32_t *len,
+                              uint64_t N, int32_t *dst, const uint64_t *dst_off, hipStream_t st)
+{
+    uint64_t blocks = (N + 3) / 4;
+    if (blocks > 65536 * 4) blocks = 65536 * 4;
+    if (blocks == 0) return hipSuccess;
+    k_copy_ragged<<<static_cast<unsigned>(blocks), 256, 0, st>>>(src, src_off, len, N, dst, dst_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_words(const int32_t *src, const uint64_t *off, const uint32_t *len,
+                               uint64_t N, int32_t *dst, const uint64_t *dst_off, hipStream_t st)
+{
+    return copy_ragged(src, off, len, N, dst, dst_off, st);
+}
+
+hipError_t launch_scatter_words(const int32_t *src, const uint64_t *src_off, const uint32_t *len,
+                                uint64_t N, int32_t *dst, const uint64_t *dst_off, hipStream_t st)
+{
+    return copy_ragged(src, src_off, len, N, dst, dst_off, st);
+}
+
+}  // namespace rasp

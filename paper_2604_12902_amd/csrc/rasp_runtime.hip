@@ -1,0 +1,856 @@
+// rasp_runtime.hip -- host side of librasp: contexts, the device arena
+// sub-allocator, batch loading, run scheduling and output fetching behind the
+// C ABI of include/rasp.h.
+#include "rasp_internal.h"
+#include "../../include/rasp.h"
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace rasp;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr int kTableRing = 16;
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// First-fit allocator over [0, size) with coalescing free list.
+class Arena {
+public:
+    void reset(uint64_t size) { free_.clear(); if (size) free_[0] = size; size_ = size; }
+    bool alloc(uint64_t bytes, uint64_t *off)
+    {
+        bytes = align_up(bytes ? bytes : 1, kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const uint64_t rest = it->second - bytes, start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t bytes)
+    {
+        bytes = align_up(bytes ? bytes : 1, kAlign);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t largest() const
+    {
+        uint64_t m = 0;
+        for (auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t size_ = 0;
+};
+
+struct Alloc {
+    uint64_t off = 0, bytes = 0;
+    bool live = false;
+};
+
+struct Batch {
+    DevBatch dev{};
+    Alloc meta, words;
+    uint64_t N = 0;
+    uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
+    bool uniform_dense = false;          // every n a multiple of 4: padded == dense
+};
+
+uint64_t meta_bytes(uint64_t N)
+{
+    // i a u0 y0 (4 each) steps (8) status (1) n ell s (4 each) mem_off t_off y_off (8 each)
+    uint64_t b = 0;
+    b += align_up(4 * N, kAlign) * 4;
+    b += align_up(8 * N, kAlign);
+    b += align_up(N, kAlign);
+    b += align_up(4 * N, kAlign) * 3;
+    b += align_up(8 * N, kAlign) * 3;
+    return b;
+}
+
+void carve_meta(char *base, uint64_t N, DevBatch *d)
+{
+    char *p = base;
+    auto take = [&](uint64_t bytes) { char *q = p; p += align_up(bytes, kAlign); return q; };
+    d->i = reinterpret_cast<int32_t *>(take(4 * N));
+    d->a = reinterpret_cast<int32_t *>(take(4 * N));
+    d->u0 = reinterpret_cast<uint32_t *>(take(4 * N));
+    d->y0 = reinterpret_cast<uint32_t *>(take(4 * N));
+    d->steps = reinterpret_cast<uint64_t *>(take(8 * N));
+    d->status = reinterpret_cast<uint8_t *>(take(N));
+    d->n = reinterpret_cast<uint32_t *>(take(4 * N));
+    d->ell = reinterpret_cast<uint32_t *>(take(4 * N));
+    d->s = reinterpret_cast<uint32_t *>(take(4 * N));
+    d->mem_off = reinterpret_cast<uint64_t *>(take(8 * N));
+    d->t_off = reinterpret_cast<uint64_t *>(take(8 * N));
+    d->y_off = reinterpret_cast<uint64_t *>(take(8 * N));
+    d->N = N;
+}
+
+uint64_t words_bytes(uint64_t sum_n_pad, uint64_t sum_ell, uint64_t sum_s)
+{
+    return align_up(4 * sum_n_pad, kAlign) + align_up(4 * sum_ell, kAlign) + align_up(4 * sum_s, kAlign);
+}
+
+void carve_words(char *base, uint64_t sum_n_pad, uint64_t sum_ell, DevBatch *d)
+{
+    d->M = reinterpret_cast<int32_t *>(base);
+    d->T = reinterpret_cast<int32_t *>(base + align_up(4 * sum_n_pad, kAlign));
+    d->Y = reinterpret_cast<int32_t *>(base + align_up(4 * sum_n_pad, kAlign) + align_up(4 * sum_ell, kAlign));
+}
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct rasp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    bool own_arena = false;
+    Arena alloc;
+    std::map<uint64_t, std::unique_ptr<Batch>> batches;
+    uint64_t next_handle = 1;
+    std::string err;
+    bool sticky = false;
+    // device properties
+    int cus = 0, lds_bytes = 0, wave = 64;
+    // options
+    int64_t schedule = RASP_SCHED_AUTO, epoch = 64, lds_words = 0, waves_per_cu = 8, graph = 0;
+    int64_t first_pass = 64;
+    // scratch: queue counters, batch tables (device ring + pinned host ring)
+    Alloc scratch;
+    QueueState *queue = nullptr;
+    BatchTable *tables = nullptr;       // kTableRing device slots
+    BatchTable *host_tables = nullptr;  // pinned
+    hipEvent_t table_ev[kTableRing] = {};
+    bool table_used[kTableRing] = {};
+    int table_next = 0;
+    Alloc work;                          // survivor list
+    uint64_t work_cap = 0;
+    uint32_t *err_host = nullptr;        // pinned: error word and totals
+    uint64_t *tot_host = nullptr;
+};
+
+namespace {
+
+int fail(rasp_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) {
+        c->err = buf;
+        if (code == RASP_E_DEVICE) c->sticky = true;
+    } else {
+        g_create_error = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return fail((c), RASP_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool arena_alloc(rasp_ctx *c, uint64_t bytes, Alloc *a)
+{
+    if (!c->alloc.alloc(bytes, &a->off)) return false;
+    a->bytes = bytes;
+    a->live = true;
+    return true;
+}
+
+void arena_free(rasp_ctx *c, Alloc *a)
+{
+    if (a->live) c->alloc.release(a->off, a->bytes);
+    a->live = false;
+}
+
+template <class T>
+T *at(rasp_ctx *c, const Alloc &a, uint64_t byte_off = 0)
+{
+    return reinterpret_cast<T *>(c->arena + a.off + byte_off);
+}
+
+int check_ctx(rasp_ctx *c)
+{
+    if (!c) return RASP_E_INVAL;
+    if (c->sticky) return RASP_E_DEVICE;
+    HIPCHK(c, hipSetDevice(c->device));
+    return RASP_OK;
+}
+
+Batch *find(rasp_ctx *c, rasp_batch b)
+{
+    auto it = c->batches.find(b);
+    return it == c->batches.end() ? nullptr : it->second.get();
+}
+
+// Host-side checks of a descriptor with host arrays; fills shapes and totals.
+struct HostShapes {
+    std::vector<uint32_t> n, ell, s;
+    std::vector<uint64_t> mem_off, t_off, y_off;
+    uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
+    uint64_t prog_words = 0, tape_words = 0;
+    bool all_n_mult4 = true;
+};
+
+int host_shapes(rasp_ctx *c, const rasp_batch_desc *d, HostShapes *h)
+{
+    const uint64_t N = d->num_vms;
+    h->n.resize(N); h->ell.resize(N); h->s.resize(N);
+    h->mem_off.resize(N); h->t_off.resize(N); h->y_off.resize(N);
+    for (uint64_t v = 0; v < N; ++v) {
+        const uint64_t p0 = d->prog_off[v], p1 = d->prog_off[v + 1];
+        const uint64_t t0 = d->tape_off[v], t1 = d->tape_off[v + 1];
+        if (p1 < p0 || t1 < t0) return fail(c, RASP_E_INVAL, "machine %llu: offsets decrease", (unsigned long long)v);
+        const uint64_t plen = p1 - p0, tlen = t1 - t0;
+        const uint32_t n = d->mem_words ? d->mem_words[v] : d->default_mem_words;
+        const uint64_t ell = d->tape_cap ? d->tape_cap[v] : tlen;
+        const uint32_t s = d->out_cap ? d->out_cap[v] : d->default_out_cap;
+        if (n == 0 || n > kMaxMemWords)
+            return fail(c, RASP_E_INVAL, "machine %llu: memory size %u outside [1, 2^30]", (unsigned long long)v, n);
+        if (plen > n)
+            return fail(c, RASP_E_INVAL, "machine %llu: program of %llu words exceeds memory of %u", (unsigned long long)v, (unsigned long long)plen, n);
+        if (tlen > ell || ell > 0x7fffffffull)
+            return fail(c, RASP_E_INVAL, "machine %llu: input of %llu words exceeds tape capacity %llu", (unsigned long long)v, (unsigned long long)tlen, (unsigned long long)ell);
+        if (s > 0x7fffffffu) return fail(c, RASP_E_INVAL, "machine %llu: output capacity too large", (unsigned long long)v);
+        h->n[v] = n; h->ell[v] = static_cast<uint32_t>(ell); h->s[v] = s;
+        h->mem_off[v] = h->sum_n_pad; h->t_off[v] = h->sum_ell; h->y_off[v] = h->sum_s;
+        h->sum_n += n; h->sum_n_pad += (n + 3u) & ~3ull; h->sum_ell += ell; h->sum_s += s;
+        if (n & 3u) h->all_n_mult4 = false;
+    }
+    h->prog_words = d->prog_off[N] - d->prog_off[0];
+    h->tape_words = d->tape_off[N] - d->tape_off[0];
+    return RASP_OK;
+}
+
+int basic_desc_checks(rasp_ctx *c, const rasp_batch_desc *d)
+{
+    if (!d) return fail(c, RASP_E_INVAL, "descriptor is NULL");
+    if (d->abi_version != RASP_ABI_VERSION) return fail(c, RASP_E_INVAL, "abi_version %u, library has %u", d->abi_version, RASP_ABI_VERSION);
+    if (d->isa != RASP_ISA_WORD && d->isa != RASP_ISA_CLASSIC) return fail(c, RASP_E_INVAL, "unknown isa %u", d->isa);
+    if (d->num_vms == 0 || d->num_vms >= (1ull << 32)) return fail(c, RASP_E_INVAL, "num_vms must be in [1, 2^32)");
+    if (!d->prog_off || !d->tape_off) return fail(c, RASP_E_INVAL, "prog_off and tape_off are required");
+    if (d->flags & ~RASP_DESC_DEVICE_PTRS) return fail(c, RASP_E_INVAL, "unknown descriptor flags");
+    return RASP_OK;
+}
+
+// Allocate and fill a batch's metadata and word arenas, then queue the pack.
+int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &out)
+{
+    int rc = basic_desc_checks(c, d);
+    if (rc) return rc;
+    const uint64_t N = d->num_vms;
+    auto B = std::make_unique<Batch>();
+    B->N = N;
+    const bool dev = (d->flags & RASP_DESC_DEVICE_PTRS) != 0;
+    hipStream_t st = c->stream;
+
+    if (!arena_alloc(c, meta_bytes(N), &B->meta))
+        return fail(c, RASP_E_NOMEM, "arena cannot hold state of %llu machines", (unsigned long long)N);
+    carve_meta(at<char>(c, B->meta), N, &B->dev);
+    B->dev.isa = d->isa;
+
+    const int32_t *prog_dev = nullptr, *tape_dev = nullptr;
+    const uint64_t *poff_dev = nullptr, *toff_dev = nullptr;
+    Alloc staging;
+
+    auto bail = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        arena_free(c, &staging);
+        arena_free(c, &B->words);
+        arena_free(c, &B->meta);
+        return code;
+    };
+
+    if (!dev) {
+        HostShapes h;
+        if ((rc = host_shapes(c, d, &h))) return bail(rc);
+        if (h.prog_words && !d->prog) { fail(c, RASP_E_INVAL, "prog is NULL"); return bail(RASP_E_INVAL); }
+        if (h.tape_words && !d->tape) { fail(c, RASP_E_INVAL, "tape is NULL"); return bail(RASP_E_INVAL); }
+        B->sum_n = h.sum_n; B->sum_n_pad = h.sum_n_pad; B->sum_ell = h.sum_ell; B->sum_s = h.sum_s;
+        B->uniform_dense = h.all_n_mult4;
+        const uint64_t sb = align_up(4 * h.prog_words, kAlign) + align_up(4 * h.tape_words, kAlign) +
+                            2 * align_up(8 * (N + 1), kAlign);
+        if (!arena_alloc(c, words_bytes(h.sum_n_pad, h.sum_ell, h.sum_s), &B->words) || !arena_alloc(c, sb, &staging)) {
+            fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)h.sum_n);
+            return bail(RASP_E_NOMEM);
+        }
+        char *sp = at<char>(c, staging);
+        int32_t *pg = reinterpret_cast<int32_t *>(sp);
+        int32_t *tp = reinterpret_cast<int32_t *>(sp + align_up(4 * h.prog_words, kAlign));
+        uint64_t *po = reinterpret_cast<uint64_t *>(sp + align_up(4 * h.prog_words, kAlign) + align_up(4 * h.tape_words, kAlign));
+        uint64_t *to = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(po) + align_up(8 * (N + 1), kAlign));
+        // offsets rebased so that the staged arrays start at 0
+        std::vector<uint64_t> po_h(N + 1), to_h(N + 1);
+        for (uint64_t v = 0; v <= N; ++v) { po_h[v] = d->prog_off[v] - d->prog_off[0]; to_h[v] = d->tape_off[v] - d->tape_off[0]; }
+        auto H2D = [&](void *dst, const void *src, uint64_t bytes) {
+            return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+        };
+        hipError_t e = hipSuccess;
+        if (!e) e = H2D(pg, d->prog + d->prog_off[0], 4 * h.prog_words);
+        if (!e) e = H2D(tp, d->tape + d->tape_off[0], 4 * h.tape_words);
+        if (!e) e = H2D(po, po_h.data(), 8 * (N + 1));
+        if (!e) e = H2D(to, to_h.data(), 8 * (N + 1));
+        if (!e) e = H2D(B->dev.n, h.n.data(), 4 * N);
+        if (!e) e = H2D(B->dev.ell, h.ell.data(), 4 * N);
+        if (!e) e = H2D(B->dev.s, h.s.data(), 4 * N);
+        if (!e) e = H2D(B->dev.mem_off, h.mem_off.data(), 8 * N);
+        if (!e) e = H2D(B->dev.t_off, h.t_off.data(), 8 * N);
+        if (!e) e = H2D(B->dev.y_off, h.y_off.data(), 8 * N);
+        carve_words(at<char>(c, B->words), B->sum_n_pad, B->sum_ell, &B->dev);
+        if (!e) e = launch_pack(B->dev, pg, po, tp, to, st);
+        // the staged copies are read by the pack kernel; sync before releasing
+        if (!e) e = hipStreamSynchronize(st);
+        if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
+        arena_free(c, &staging);
+    } else {
+        // device descriptor: checks, shapes and offsets computed on the device
+        const uint64_t nsc = scan_scratch_words(N);
+        const uint64_t tb = align_up(8 * N, kAlign) + 3 * align_up(8 * nsc, kAlign) + kAlign;
+        if (!arena_alloc(c, tb, &staging)) { fail(c, RASP_E_NOMEM, "arena cannot hold load scratch"); return bail(RASP_E_NOMEM); }
+        char *sp = at<char>(c, staging);
+        uint64_t *n_pad = reinterpret_cast<uint64_t *>(sp);
+        uint64_t *sums = reinterpret_cast<uint64_t *>(sp + align_up(8 * N, kAlign));
+        uint64_t *tots = reinterpret_cast<uint64_t *>(sp + align_up(8 * N, kAlign) + 3 * align_up(8 * nsc, kAlign));
+        uint32_t *errw = reinterpret_cast<uint32_t *>(tots + 4);
+        hipError_t e = hipMemsetAsync(tots, 0, kAlign, st);
+        if (!e) e = launch_shapes(d->prog_off, d->tape_off, d->mem_words, d->default_mem_words, d->tape_cap,
+                                  d->out_cap, d->default_out_cap, N, B->dev.n, B->dev.ell, B->dev.s, n_pad, errw, st);
+        if (!e) e = launch_scan_u64(n_pad, B->dev.mem_off, N, sums, &tots[0], st);
+        if (!e) e = launch_scan_u32(B->dev.ell, B->dev.t_off, N, sums + align_up(8 * nsc, kAlign) / 8, &tots[1], st);
+        if (!e) e = launch_scan_u32(B->dev.s, B->dev.y_off, N, sums + 2 * align_up(8 * nsc, kAlign) / 8, &tots[2], st);
+        if (!e) e = launch_scan_u32(B->dev.n, n_pad, N, sums, &tots[3], st);   // dense total into tots[3]
+        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (!e) e = hipStreamSynchronize(st);
+        if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
+        uint32_t errbits;
+        std::memcpy(&errbits, reinterpret_cast<char *>(c->tot_host) + 32, 4);
+        if (errbits) {
+            fail(c, RASP_E_INVAL, "descriptor check failed (bits 0x%x: 1 offsets, 2 program > memory, 4 input > tape, 8 memory size)", errbits);
+            return bail(RASP_E_INVAL);
+        }
+        B->sum_n_pad = c->tot_host[0]; B->sum_ell = c->tot_host[1]; B->sum_s = c->tot_host[2]; B->sum_n = c->tot_host[3];
+        B->uniform_dense = (B->sum_n == B->sum_n_pad);
+        if (!arena_alloc(c, words_bytes(B->sum_n_pad, B->sum_ell, B->sum_s), &B->words)) {
+            fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)B->sum_n);
+            return bail(RASP_E_NOMEM);
+        }
+        carve_words(at<char>(c, B->words), B->sum_n_pad, B->sum_ell, &B->dev);
+        prog_dev = d->prog; tape_dev = d->tape; poff_dev = d->prog_off; toff_dev = d->tape_off;
+        e = launch_pack(B->dev, prog_dev, poff_dev, tape_dev, toff_dev, st);
+        if (e) { fail(c, RASP_E_DEVICE, "pack: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
+        // scratch is only used by work queued before this point: stream order makes reuse safe
+        arena_free(c, &staging);
+    }
+    out = std::move(B);
+    return RASP_OK;
+}
+
+// ensure the survivor list holds `items` entries
+int ensure_work(rasp_ctx *c, uint64_t items)
+{
+    if (items <= c->work_cap) return RASP_OK;
+    if (c->work.live) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        arena_free(c, &c->work);
+    }
+    if (!arena_alloc(c, 4 * items, &c->work)) {
+        c->work_cap = 0;
+        return fail(c, RASP_E_NOMEM, "arena cannot hold the work list of %llu machines", (unsigned long long)items);
+    }
+    c->work_cap = items;
+    return RASP_OK;
+}
+
+// grab a device batch-table slot and its pinned host mirror
+int table_slot(rasp_ctx *c, BatchTable **host, BatchTable **devp, int *slot)
+{
+    const int k = c->table_next;
+    c->table_next = (k + 1) % kTableRing;
+    if (c->table_used[k]) HIPCHK(c, hipEventSynchronize(c->table_ev[k]));
+    *host = &c->host_tables[k];
+    *devp = &c->tables[k];
+    *slot = k;
+    return RASP_OK;
+}
+
+int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
+{
+    const uint32_t isa = bs[0]->dev.isa;
+    for (uint32_t t = 1; t < k; ++t)
+        if (bs[t]->dev.isa != isa) return fail(c, RASP_E_INVAL, "batches of one launch must share the instruction set");
+    BatchTable *ht, *dt;
+    int slot;
+    int rc = table_slot(c, &ht, &dt, &slot);
+    if (rc) return rc;
+    std::memset(ht, 0, sizeof(BatchTable));
+    uint64_t total = 0;
+    uint32_t maxb = 0;
+    for (uint32_t t = 0; t < k; ++t) {
+        ht->b[t] = bs[t]->dev;
+        ht->start[t] = total;
+        ht->budget[t] = budgets[t];
+        total += bs[t]->N;
+        maxb = std::max(maxb, budgets[t]);
+    }
+    ht->start[k] = total;
+    ht->count = k;
+    if (total >= (1ull << 32)) return fail(c, RASP_E_INVAL, "too many machines in one launch");
+    if (maxb == 0) return RASP_OK;
+    hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
+    c->table_used[slot] = true;
+    HIPCHK(c, launch_zero_queue(c->queue, st));
+
+    int64_t sched = c->schedule;
+    if (sched == RASP_SCHED_AUTO) sched = RASP_SCHED_PERSISTENT;
+    if (sched == RASP_SCHED_PLAIN) {
+        HIPCHK(c, launch_plain(dt, total, maxb, isa, nullptr, c->queue, st));
+        return RASP_OK;
+    }
+    // persistent: a first plain pass of `first_pass` steps retires the short
+    // runners; the survivors go through the persistent kernel
+    const uint32_t cap = static_cast<uint32_t>(std::max<int64_t>(0, c->first_pass));
+    // waves per block: as many (up to 4) as the LDS slots of one block allow
+    uint32_t P = static_cast<uint32_t>(std::max<int64_t>(0, c->lds_words));
+    const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
+    while (P && static_cast<uint64_t>(kWave) * P * 4 > lds) P >>= 1;
+    uint32_t wpb = 4;
+    while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * P * 4 > lds) wpb >>= 1;
+    const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
+    const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
+    const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
+    if (cap > 0 && cap < maxb) {
+        if ((rc = ensure_work(c, total))) return rc;
+        uint32_t *work = at<uint32_t>(c, c->work);
+        HIPCHK(c, launch_plain(dt, total, cap, isa, work, c->queue, st));
+        HIPCHK(c, launch_persistent(dt, total, work, cap, isa, epoch, P, wpb, blocks, c->queue, st));
+    } else if (cap >= maxb) {
+        HIPCHK(c, launch_plain(dt, total, maxb, isa, nullptr, c->queue, st));
+    } else {
+        HIPCHK(c, launch_persistent(dt, total, nullptr, 0, isa, epoch, P, wpb, blocks, c->queue, st));
+    }
+    return RASP_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, void *stream)
+{
+    if (!out) return fail(nullptr, RASP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (arena_bytes < (1ull << 20)) return fail(nullptr, RASP_E_INVAL, "arena must be at least 1 MiB");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, RASP_E_INVAL, "no HIP device %d", device);
+    auto c = std::unique_ptr<rasp_ctx>(new (std::nothrow) rasp_ctx());
+    if (!c) return fail(nullptr, RASP_E_NOMEM, "host allocation failed");
+    c->device = device;
+    hipError_t e = hipSetDevice(device);
+    hipDeviceProp_t prop;
+    if (!e) e = hipGetDeviceProperties(&prop, device);
+    if (e) return fail(nullptr, RASP_E_DEVICE, "device query: %s", hipGetErrorString(e));
+    c->cus = prop.multiProcessorCount;
+    c->wave = prop.warpSize;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+    c->lds_bytes = lds;
+    if (c->wave != kWave) return fail(nullptr, RASP_E_DEVICE, "wavefront size %d, library built for 64", c->wave);
+    if (stream) {
+        c->stream = static_cast<hipStream_t>(stream);
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e) return fail(nullptr, RASP_E_DEVICE, "stream: %s", hipGetErrorString(e));
+        c->own_stream = true;
+    }
+    if (arena) {
+        c->arena = static_cast<char *>(arena);
+    } else {
+        e = hipMalloc(reinterpret_cast<void **>(&c->arena), arena_bytes);
+        if (e) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            return fail(nullptr, RASP_E_NOMEM, "arena hipMalloc(%llu): %s", (unsigned long long)arena_bytes, hipGetErrorString(e));
+        }
+        c->own_arena = true;
+    }
+    c->arena_bytes = arena_bytes;
+    c->alloc.reset(arena_bytes);
+    const uint64_t sbytes = align_up(sizeof(QueueState), kAlign) + kTableRing * align_up(sizeof(BatchTable), kAlign);
+    bool ok = arena_alloc(c.get(), sbytes, &c->scratch);
+    if (ok) {
+        c->queue = at<QueueState>(c.get(), c->scratch);
+        c->tables = at<BatchTable>(c.get(), c->scratch, align_up(sizeof(QueueState), kAlign));
+    }
+    e = ok ? hipHostMalloc(reinterpret_cast<void **>(&c->host_tables), kTableRing * sizeof(BatchTable), hipHostMallocDefault) : hipErrorOutOfMemory;
+    if (!e) e = hipHostMalloc(reinterpret_cast<void **>(&c->tot_host), 64, hipHostMallocDefault);
+    for (int k = 0; k < kTableRing && !e; ++k) e = hipEventCreateWithFlags(&c->table_ev[k], hipEventDisableTiming);
+    if (e) {
+        rasp_destroy(c.release());
+        return fail(nullptr, RASP_E_DEVICE, "context scratch: %s", hipGetErrorString(e));
+    }
+    // defaults: stage the whole memory in LDS when it is small
+    c->lds_words = 0;
+    *out = c.release();
+    return RASP_OK;
+}
+
+int rasp_destroy(rasp_ctx *c)
+{
+    if (!c) return RASP_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < kTableRing; ++k)
+        if (c->table_ev[k]) (void)hipEventDestroy(c->table_ev[k]);
+    if (c->host_tables) (void)hipHostFree(c->host_tables);
+    if (c->tot_host) (void)hipHostFree(c->tot_host);
+    if (c->own_arena && c->arena) (void)hipFree(c->arena);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return RASP_OK;
+}
+
+const char *rasp_last_error(const rasp_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+int rasp_batch_footprint(const rasp_batch_desc *d, uint64_t *bytes)
+{
+    rasp_ctx tmp;                       // only for error text
+    int rc = basic_desc_checks(&tmp, d);
+    if (rc) return rc;
+    if (!bytes) return RASP_E_INVAL;
+    const uint64_t N = d->num_vms;
+    uint64_t sum_n_pad = 0, sum_ell = 0, sum_s = 0;
+    if (d->flags & RASP_DESC_DEVICE_PTRS) {
+        std::vector<uint64_t> to(N + 1);
+        std::vector<uint32_t> nn, tc, oc;
+        if (hipMemcpy(to.data(), d->tape_off, 8 * (N + 1), hipMemcpyDeviceToHost) != hipSuccess) return RASP_E_DEVICE;
+        if (d->mem_words) { nn.resize(N); if (hipMemcpy(nn.data(), d->mem_words, 4 * N, hipMemcpyDeviceToHost)) return RASP_E_DEVICE; }
+        if (d->tape_cap) { tc.resize(N); if (hipMemcpy(tc.data(), d->tape_cap, 4 * N, hipMemcpyDeviceToHost)) return RASP_E_DEVICE; }
+        if (d->out_cap) { oc.resize(N); if (hipMemcpy(oc.data(), d->out_cap, 4 * N, hipMemcpyDeviceToHost)) return RASP_E_DEVICE; }
+        for (uint64_t v = 0; v < N; ++v) {
+            const uint64_t n = nn.empty() ? d->default_mem_words : nn[v];
+            sum_n_pad += (n + 3) & ~3ull;
+            sum_ell += tc.empty() ? (to[v + 1] - to[v]) : tc[v];
+            sum_s += oc.empty() ? d->default_out_cap : oc[v];
+        }
+    } else {
+        HostShapes h;
+        if ((rc = host_shapes(&tmp, d, &h))) return rc;
+        sum_n_pad = h.sum_n_pad; sum_ell = h.sum_ell; sum_s = h.sum_s;
+    }
+    *bytes = meta_bytes(N) + words_bytes(sum_n_pad, sum_ell, sum_s);
+    return RASP_OK;
+}
+
+int rasp_load_batch(rasp_ctx *c, const rasp_batch_desc *d, rasp_batch *out)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out) return fail(c, RASP_E_INVAL, "out is NULL");
+    std::unique_ptr<Batch> B;
+    if ((rc = load_common(c, d, B))) return rc;
+    const rasp_batch h = c->next_handle++;
+    c->batches[h] = std::move(B);
+    *out = h;
+    return RASP_OK;
+}
+
+int rasp_load_state(rasp_ctx *c, const rasp_batch_desc *d, const rasp_outputs *s, rasp_batch *out)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out || !s || !s->mem || !s->i || !s->a || !s->u0 || !s->y0)
+        return fail(c, RASP_E_INVAL, "state needs i, a, u0, y0 and mem");
+    std::unique_ptr<Batch> B;
+    if ((rc = load_common(c, d, B))) return rc;
+    Batch &b = *B;
+    hipStream_t st = c->stream;
+    const hipMemcpyKind kind = (s->flags & RASP_OUT_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const uint64_t N = b.N;
+    Alloc tmp;
+    auto undo = [&](int code) {
+        (void)hipStreamSynchronize(st);
+        arena_free(c, &tmp);
+        arena_free(c, &b.words);
+        arena_free(c, &b.meta);
+        return code;
+    };
+    hipError_t e = hipMemcpyAsync(b.dev.i, s->i, 4 * N, kind, st);
+    if (!e) e = hipMemcpyAsync(b.dev.a, s->a, 4 * N, kind, st);
+    if (!e) e = hipMemcpyAsync(b.dev.u0, s->u0, 4 * N, kind, st);
+    if (!e) e = hipMemcpyAsync(b.dev.y0, s->y0, 4 * N, kind, st);
+    if (!e && s->steps) e = hipMemcpyAsync(b.dev.steps, s->steps, 8 * N, kind, st);
+    if (!e && s->y && b.sum_s) e = hipMemcpyAsync(b.dev.Y, s->y, 4 * b.sum_s, kind, st);
+    if (e) { fail(c, RASP_E_DEVICE, "state copy: %s", hipGetErrorString(e)); return undo(RASP_E_DEVICE); }
+    if (b.uniform_dense) {
+        e = hipMemcpyAsync(b.dev.M, s->mem, 4 * b.sum_n, kind, st);
+    } else {
+        // dense machine-major memory -> padded arena
+        const uint64_t nsc = scan_scratch_words(N);
+        const uint64_t tb = align_up(8 * N, kAlign) + align_up(8 * nsc, kAlign) + kAlign + align_up(4 * b.sum_n, kAlign);
+        if (!arena_alloc(c, tb, &tmp)) { fail(c, RASP_E_NOMEM, "arena cannot stage the state"); return undo(RASP_E_NOMEM); }
+        uint64_t *doff = at<uint64_t>(c, tmp);
+        uint64_t *sums = at<uint64_t>(c, tmp, align_up(8 * N, kAlign));
+        uint64_t *tot = at<uint64_t>(c, tmp, align_up(8 * N, kAlign) + align_up(8 * nsc, kAlign));
+        int32_t *dense = at<int32_t>(c, tmp, align_up(8 * N, kAlign) + align_up(8 * nsc, kAlign) + kAlign);
+        e = launch_scan_u32(b.dev.n, doff, N, sums, tot, st);
+        if (!e) e = hipMemcpyAsync(dense, s->mem, 4 * b.sum_n, kind, st);
+        if (!e) e = launch_scatter_words(dense, doff, b.dev.n, N, b.dev.M, b.dev.mem_off, st);
+    }
+    uint32_t *errw = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(c->tot_host) + 32);
+    if (!e) { *errw = 0; }
+    // the error word lives in the queue scratch to avoid another allocation
+    uint32_t *derr = reinterpret_cast<uint32_t *>(&c->queue->pad);
+    if (!e) e = hipMemsetAsync(derr, 0, 4, st);
+    if (!e) e = launch_check_state(b.dev, derr, st);
+    if (!e) e = launch_probe(b.dev, st);
+    if (!e) e = hipMemcpyAsync(errw, derr, 4, hipMemcpyDeviceToHost, st);
+    if (!e) e = hipStreamSynchronize(st);
+    if (e) { fail(c, RASP_E_DEVICE, "state load: %s", hipGetErrorString(e)); return undo(RASP_E_DEVICE); }
+    if (*errw) { fail(c, RASP_E_INVAL, "state has u0 > l or y0 > s"); return undo(RASP_E_INVAL); }
+    arena_free(c, &tmp);
+    const rasp_batch h = c->next_handle++;
+    c->batches[h] = std::move(B);
+    *out = h;
+    return RASP_OK;
+}
+
+int rasp_run(rasp_ctx *c, rasp_batch h, uint64_t budget)
+{
+    return rasp_run_multi(c, &h, &budget, 1);
+}
+
+int rasp_run_multi(rasp_ctx *c, const rasp_batch *hs, const uint64_t *budgets, uint32_t k)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!hs || !budgets || k == 0 || k > static_cast<uint32_t>(kMaxMulti))
+        return fail(c, RASP_E_INVAL, "rasp_run_multi takes 1..%d batches", kMaxMulti);
+    std::vector<Batch *> bs(k);
+    std::vector<uint64_t> left(budgets, budgets + k);
+    for (uint32_t t = 0; t < k; ++t) {
+        bs[t] = find(c, hs[t]);
+        if (!bs[t]) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)hs[t]);
+        for (uint32_t u = 0; u < t; ++u)
+            if (hs[u] == hs[t]) return fail(c, RASP_E_INVAL, "batch %llu listed twice", (unsigned long long)hs[t]);
+    }
+    // budgets above 2^31 - 1 are applied in several launches (runs compose)
+    const uint64_t chunk = 0x7fffffffull;
+    for (;;) {
+        std::vector<uint32_t> b32(k);
+        bool any = false;
+        for (uint32_t t = 0; t < k; ++t) {
+            const uint64_t x = std::min(left[t], chunk);
+            b32[t] = static_cast<uint32_t>(x);
+            left[t] -= x;
+            any |= x > 0;
+        }
+        if (!any) break;
+        if ((rc = run_batches(c, bs.data(), b32.data(), k))) return rc;
+    }
+    return RASP_OK;
+}
+
+int rasp_poll(rasp_ctx *c, int *done)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!done) return fail(c, RASP_E_INVAL, "done is NULL");
+    const hipError_t e = hipStreamQuery(c->stream);
+    if (e == hipSuccess) { *done = 1; return RASP_OK; }
+    if (e == hipErrorNotReady) { *done = 0; return RASP_OK; }
+    return fail(c, RASP_E_DEVICE, "stream query: %s", hipGetErrorString(e));
+}
+
+int rasp_sync(rasp_ctx *c)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RASP_OK;
+}
+
+int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Batch *b = find(c, h);
+    if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
+    if (!o) return fail(c, RASP_E_INVAL, "outputs is NULL");
+    hipStream_t st = c->stream;
+    const hipMemcpyKind kind = (o->flags & RASP_OUT_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const uint64_t N = b->N;
+    if (o->status) HIPCHK(c, hipMemcpyAsync(o->status, b->dev.status, N, kind, st));
+    if (o->steps) HIPCHK(c, hipMemcpyAsync(o->steps, b->dev.steps, 8 * N, kind, st));
+    if (o->i) HIPCHK(c, hipMemcpyAsync(o->i, b->dev.i, 4 * N, kind, st));
+    if (o->a) HIPCHK(c, hipMemcpyAsync(o->a, b->dev.a, 4 * N, kind, st));
+    if (o->u0) HIPCHK(c, hipMemcpyAsync(o->u0, b->dev.u0, 4 * N, kind, st));
+    if (o->y0) HIPCHK(c, hipMemcpyAsync(o->y0, b->dev.y0, 4 * N, kind, st));
+    if (o->y && b->sum_s) HIPCHK(c, hipMemcpyAsync(o->y, b->dev.Y, 4 * b->sum_s, kind, st));
+    Alloc tmp;
+    if (o->mem_digest) {
+        if (kind == hipMemcpyDeviceToDevice) {
+            HIPCHK(c, launch_digest(b->dev, o->mem_digest, st));
+        } else {
+            if (!arena_alloc(c, 8 * N, &tmp)) return fail(c, RASP_E_NOMEM, "arena cannot hold digests");
+            HIPCHK(c, launch_digest(b->dev, at<uint64_t>(c, tmp), st));
+            HIPCHK(c, hipMemcpyAsync(o->mem_digest, at<uint64_t>(c, tmp), 8 * N, kind, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            arena_free(c, &tmp);
+        }
+    }
+    if (o->mem) {
+        if (b->uniform_dense) {
+            HIPCHK(c, hipMemcpyAsync(o->mem, b->dev.M, 4 * b->sum_n, kind, st));
+        } else {
+            // padded arena -> dense machine-major, through an arena buffer
+            const uint64_t nsc = scan_scratch_words(N);
+            const uint64_t tb = align_up(8 * N, kAlign) + align_up(8 * nsc, kAlign) + kAlign +
+                                (kind == hipMemcpyDeviceToDevice ? 0 : align_up(4 * b->sum_n, kAlign));
+            if (!arena_alloc(c, tb, &tmp)) return fail(c, RASP_E_NOMEM, "arena cannot stage the memory dump");
+            uint64_t *doff = at<uint64_t>(c, tmp);
+            uint64_t *sums = at<uint64_t>(c, tmp, align_up(8 * N, kAlign));
+            uint64_t *tot = at<uint64_t>(c, tmp, align_up(8 * N, kAlign) + align_up(8 * nsc, kAlign));
+            int32_t *dense = kind == hipMemcpyDeviceToDevice
+                                 ? o->mem
+                                 : at<int32_t>(c, tmp, align_up(8 * N, kAlign) + align_up(8 * nsc, kAlign) + kAlign);
+            HIPCHK(c, launch_scan_u32(b->dev.n, doff, N, sums, tot, st));
+            HIPCHK(c, launch_gather_words(b->dev.M, b->dev.mem_off, b->dev.n, N, dense, doff, st));
+            if (kind != hipMemcpyDeviceToDevice)
+                HIPCHK(c, hipMemcpyAsync(o->mem, dense, 4 * b->sum_n, kind, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            arena_free(c, &tmp);
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    return RASP_OK;
+}
+
+int rasp_batch_info(rasp_ctx *c, rasp_batch h, uint64_t *num_vms, uint64_t *mem_words,
+                    uint64_t *out_words, uint64_t *steps_sum)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Batch *b = find(c, h);
+    if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
+    if (num_vms) *num_vms = b->N;
+    if (mem_words) *mem_words = b->sum_n;
+    if (out_words) *out_words = b->sum_s;
+    if (steps_sum) {
+        unsigned long long *d = reinterpret_cast<unsigned long long *>(&c->queue->retired);
+        HIPCHK(c, hipMemsetAsync(d, 0, 8, c->stream));
+        HIPCHK(c, launch_steps_sum(b->dev, d, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->tot_host, d, 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *steps_sum = c->tot_host[0];
+    }
+    return RASP_OK;
+}
+
+int rasp_free_batch(rasp_ctx *c, rasp_batch h)
+{
+    if (!c) return RASP_E_INVAL;
+    auto it = c->batches.find(h);
+    if (it == c->batches.end()) return fail(c, RASP_E_STATE, "unknown or freed batch handle %llu", (unsigned long long)h);
+    // later work on the same stream may reuse the space only after this batch's
+    // queued work: stream order guarantees it
+    arena_free(c, &it->second->words);
+    arena_free(c, &it->second->meta);
+    c->batches.erase(it);
+    return RASP_OK;
+}
+
+int rasp_set_option(rasp_ctx *c, int option, int64_t value)
+{
+    if (!c) return RASP_E_INVAL;
+    switch (option) {
+    case RASP_OPT_SCHEDULE:
+        if (value < RASP_SCHED_AUTO || value > RASP_SCHED_PERSISTENT) return fail(c, RASP_E_INVAL, "bad schedule");
+        c->schedule = value; return RASP_OK;
+    case RASP_OPT_EPOCH:
+        if (value < 1 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "epoch must be >= 1");
+        c->epoch = value; return RASP_OK;
+    case RASP_OPT_LDS_WORDS:
+        if (value < 0 || value > 1024 || (value & (value - 1))) return fail(c, RASP_E_INVAL, "lds words must be 0 or a power of two <= 1024");
+        c->lds_words = value; return RASP_OK;
+    case RASP_OPT_WAVES_PER_CU:
+        if (value < 1 || value > 32) return fail(c, RASP_E_INVAL, "waves per CU must be in [1, 32]");
+        c->waves_per_cu = value; return RASP_OK;
+    case RASP_OPT_GRAPH:
+        c->graph = value ? 1 : 0; return RASP_OK;
+    case RASP_OPT_FIRST_PASS:
+        if (value < 0 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "first pass must be >= 0");
+        c->first_pass = value; return RASP_OK;
+    default:
+        return fail(c, RASP_E_INVAL, "unknown option %d", option);
+    }
+}
+
+int rasp_get_option(rasp_ctx *c, int option, int64_t *value)
+{
+    if (!c || !value) return RASP_E_INVAL;
+    switch (option) {
+    case RASP_OPT_SCHEDULE: *value = c->schedule; return RASP_OK;
+    case RASP_OPT_EPOCH: *value = c->epoch; return RASP_OK;
+    case RASP_OPT_LDS_WORDS: *value = c->lds_words; return RASP_OK;
+    case RASP_OPT_WAVES_PER_CU: *value = c->waves_per_cu; return RASP_OK;
+    case RASP_OPT_GRAPH: *value = c->graph; return RASP_OK;
+    case RASP_OPT_FIRST_PASS: *value = c->first_pass; return RASP_OK;
+    default: return fail(c, RASP_E_INVAL, "unknown option %d", option);
+    }
+}
+
+int rasp_device_info(rasp_ctx *c, int *cus, int *lds_bytes, int *wave_size)
+{
+    if (!c) return RASP_E_INVAL;
+    if (cus) *cus = c->cus;
+    if (lds_bytes) *lds_bytes = c->lds_bytes;
+    if (wave_size) *wave_size = c->wave;
+    return RASP_OK;
+}
+
+}  // extern "C"

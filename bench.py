@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Benchmark: VM instructions retired per second on one MI355X, bit-exact.
+
+One step = one pass of the whole hot path over one batch of synthetic
+machines whose packed programs and tapes are already resident in HBM:
+  rasp_load_batch (device descriptor: checks, offsets, c0 pack)
+  rasp_run(budget) (plain, or first plain pass + persistent work-queue kernel)
+  rasp_fetch_outputs into device-resident buffers (status, steps, i, a, u0,
+  y0 and the output words)
+  rasp_free_batch.
+The value is the sum of retired transitions of the batch divided by the mean
+step time.  Before reporting, the final state of every machine is checked
+against the CPU oracle (the oracle is run on the same batch on the host; its
+timing is the cpu_baseline).
+
+Workloads (sizes of the stated populations):
+  plain-scale  1,048,576 random programs x 64 instructions, n = 256,
+               tape 32 words, output capacity 16, budget 4,096 (default)
+  plain-small  4,096 x 16 instructions, n = 32, budget 256
+  uneven       4,194,304 programs of 8..512 instructions, budget 65,536
+  rollouts     262,144 counted-loop array programs, n = 2,048, budget 2^20
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="plain-scale",
+                    choices=["plain-scale", "plain-small", "uneven", "rollouts"])
+    ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-schedule comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verify", choices=["full", "sample", "none"], default="full")
+    ap.add_argument("--first-pass", type=int, default=None)
+    ap.add_argument("--lds-words", type=int, default=None)
+    ap.add_argument("--epoch", type=int, default=None)
+    ap.add_argument("--waves-per-cu", type=int, default=None)
+    ap.add_argument("--json-extra", default="", help="path to write the full report")
+    return ap.parse_args()
+
+
+def make_batch(args):
+    from paper_2604_12902_amd import workloads as W
+    kw = {}
+    if args.num_vms:
+        kw["num_vms"] = args.num_vms
+    if args.workload == "plain-scale":
+        return W.config2(**kw)
+    if args.workload == "plain-small":
+        return W.config1(**kw)
+    if args.workload == "uneven":
+        return W.config3(**kw)
+    return W.config4(**kw)
+
+
+def bytes_per_step(mix: np.ndarray) -> float:
+    """Algorithmic bytes per retired step for a retired-opcode mix:
+    8 B fetch (opcode + operand) always; +4 B data read for ADD/SUB/MUL and
+    PRINT; +4 B data write for STORE; READ +4 B tape read +4 B memory write;
+    an appended PRINT +4 B output write."""
+    steps = float(mix[1:9].sum())
+    if steps == 0:
+        return 0.0
+    extra = 4.0 * (mix[2] + mix[3] + mix[7]) + 4.0 * mix[4] + 8.0 * mix[6] + 4.0 * mix[9]
+    return 8.0 + float(extra) / steps
+
+
+def pack_bytes(batch) -> int:
+    """Algorithmic bytes of building c0: read the program and input words,
+    write n + l + s words and the 25 B of scalars (i, a, u0, y0, steps,
+    status) per machine."""
+    N = batch.N
+    return int(4 * batch.prog.size + 4 * batch.tape.size +
+               4 * (batch.mem_words.astype(np.int64).sum() + batch.tape_cap.astype(np.int64).sum()
+                    + batch.out_cap.astype(np.int64).sum()) + 25 * N)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path is data-parallel over "
+              "independent machines and this build has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_2604_12902_amd import rasp as R
+
+    t_gen = time.time()
+    batch = make_batch(args)
+    budget = batch.budget
+    gen_s = time.time() - t_gen
+    print("bench: workload %s N=%d budget=%d (generated in %.1f s, sha256 %s)" % (
+        args.workload, batch.N, budget, gen_s, batch.sha256()[:16]), flush=True)
+
+    # ---- CPU oracle: the reference result and the CPU baseline ----
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 64))
+    t0 = time.time()
+    ref = oracle.init(batch)
+    mix = oracle.advance_mix(ref, budget, threads=cores)
+    cpu_s = time.time() - t0
+    total_steps = int(ref.steps.sum())
+    bstep = bytes_per_step(mix)
+    print("bench: oracle %d threads %.2f s, %d retired steps, %.2f algorithmic B/step" % (
+        cores, cpu_s, total_steps, bstep), flush=True)
+
+    dev = torch.device("cuda", 0)
+    desc = R.make_desc(batch, dev)                     # inputs resident in HBM
+    N = batch.N
+    outs = dict(status=torch.empty(N, dtype=torch.uint8, device=dev),
+                steps=torch.empty(N, dtype=torch.int64, device=dev),
+                i=torch.empty(N, dtype=torch.int32, device=dev),
+                a=torch.empty(N, dtype=torch.int32, device=dev),
+                u0=torch.empty(N, dtype=torch.int32, device=dev),
+                y0=torch.empty(N, dtype=torch.int32, device=dev),
+                y=torch.empty(int(batch.out_cap.astype(np.int64).sum()), dtype=torch.int32, device=dev))
+    fp = R.rasp_batch_footprint(desc)
+    arena = int(fp * 1.25) + (256 << 20)
+    ctx = R.Context(arena)
+    torch.cuda.synchronize()
+
+    def configure(schedule):
+        ctx.set(R.RASP_OPT_SCHEDULE, schedule)
+        if args.first_pass is not None:
+            ctx.set(R.RASP_OPT_FIRST_PASS, args.first_pass)
+        if args.lds_words is not None:
+            ctx.set(R.RASP_OPT_LDS_WORDS, args.lds_words)
+        if args.epoch is not None:
+            ctx.set(R.RASP_OPT_EPOCH, args.epoch)
+        if args.waves_per_cu is not None:
+            ctx.set(R.RASP_OPT_WAVES_PER_CU, args.waves_per_cu)
+
+    def one_step(keep=False):
+        h = R.rasp_load_batch(ctx.handle, desc)
+        R.rasp_run(ctx.handle, h, budget)
+        R.rasp_fetch_outputs_into(ctx.handle, h, outs, device=True)
+        if keep:
+            return h
+        R.rasp_free_batch(ctx.handle, h)
+        return None
+
+    def timed(schedule):
+        configure(schedule)
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        ctx.set(R.RASP_OPT_PROFILE, 1)
+        R.rasp_kernel_times(ctx.handle)                 # reset
+        per = []
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            s0 = time.perf_counter()
+            one_step()
+            per.append(time.perf_counter() - s0)        # fetch_outputs waits for the step
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        kt = R.rasp_kernel_times(ctx.handle)
+        ctx.set(R.RASP_OPT_PROFILE, 0)
+        return wall, np.array(per), kt
+
+    def verify():
+        h = one_step(keep=True)
+        got = R.rasp_fetch_outputs(ctx.handle, h, mem=(args.verify == "full"))
+        R.rasp_free_batch(ctx.handle, h)
+        for k in ("status", "steps", "i", "a", "u0", "y0"):
+            if not np.array_equal(got[k], getattr(ref, k)):
+                bad = np.flatnonzero(got[k] != getattr(ref, k))
+                raise SystemExit("bench: NOT bit-exact: %s differs at %d machines (first %s)" % (
+                    k, bad.size, bad[:5]))
+        if not np.array_equal(got["y"], ref.Y):
+            raise SystemExit("bench: NOT bit-exact: output words differ")
+        if args.verify == "full" and not np.array_equal(got["mem"], ref.mem):
+            raise SystemExit("bench: NOT bit-exact: memory differs")
+
+    results = {}
+    for name, sched in (("persistent", R.RASP_SCHED_PERSISTENT), ("plain", R.RASP_SCHED_PLAIN)):
+        if name == "plain" and args.no_plain:
+            continue
+        wall, per, kt = timed(sched)
+        if args.verify != "none":
+            verify()
+        ms = 1e3 * wall / args.steps
+        results[name] = dict(ms_per_step=ms, value=total_steps / (wall / args.steps),
+                             p50_ms=float(np.percentile(per, 50) * 1e3),
+                             p99_ms=float(np.percentile(per, 99) * 1e3), kernels=kt)
+        print("bench: %-10s %.3f ms/step  %.3e steps/s  p50 %.3f p99 %.3f ms  kernels %s" % (
+            name, ms, results[name]["value"], results[name]["p50_ms"], results[name]["p99_ms"],
+            {k: "%.3f ms x%d" % (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1]}),
+            flush=True)
+
+    head = results["persistent"]
+    kt = head["kernels"]
+    # dominant kernel of the headline schedule: largest total time
+    dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
+    dom_ms = kt[dom][0] / kt[dom][1]
+    fp_pass = int(ctx.get(R.RASP_OPT_FIRST_PASS))
+    steps_plain_pass = int(np.minimum(ref.steps.astype(np.int64), fp_pass).sum())
+    if dom == "pack":
+        algo = pack_bytes(batch)
+        unit_note = "c0 bytes: programs + inputs read, n+l+s words + 25 B scalars written per machine"
+    elif dom == "persistent":
+        algo = bstep * (total_steps - steps_plain_pass) + 50.0 * int((ref.steps > fp_pass).sum())
+        unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
+    elif dom == "plain":
+        algo = bstep * steps_plain_pass + 50.0 * N
+        unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
+    else:
+        algo = 0.0
+        unit_note = "n/a"
+    achieved = algo / (dom_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": dom, "kernel_ms": round(dom_ms, 4), "algorithmic_bytes": int(algo),
+            "per_unit": unit_note}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = {"value": total_steps / cpu_s, "unit": "VM instructions retired/s", "cores": cores,
+               "kind": "oracle",
+               "sample": "the whole batch (%d machines, %d retired steps), %d host threads, "
+                         "static round-robin striping" % (N, total_steps, cores)}
+
+    line = {
+        "metric": "VM instructions retired/sec (1 GPU), bit-exact; persistent vs plain; p50/p99",
+        "value": head["value"], "unit": "VM instructions retired/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic (seeded random RASP programs)",
+        "config": {"workload": batch.name, "num_vms": N, "budget": budget,
+                   "retired_steps_per_batch": total_steps, "schedule": "persistent",
+                   "first_pass": fp_pass, "lds_words": int(ctx.get(R.RASP_OPT_LDS_WORDS)),
+                   "epoch": int(ctx.get(R.RASP_OPT_EPOCH)),
+                   "waves_per_cu": int(ctx.get(R.RASP_OPT_WAVES_PER_CU))},
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "plain": ({k: results["plain"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms")}
+                  if "plain" in results else None),
+        "bit_exact": args.verify,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if args.json_extra:
+        with open(args.json_extra, "w") as f:
+            json.dump(dict(line=line, results={k: {kk: vv for kk, vv in v.items()}
+                                               for k, v in results.items()}), f, indent=1)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -261,6 +261,24 @@ enum { RASP_SCHED_AUTO = 0, RASP_SCHED_PLAIN = 1, RASP_SCHED_PERSISTENT = 2 };
 int rasp_set_option(rasp_ctx *ctx, int option, int64_t value);
 int rasp_get_option(rasp_ctx *ctx, int option, int64_t *value);
 
+/*
+ * Kernel timing.  With RASP_OPT_PROFILE set to 1 the context records a pair of
+ * HIP events on its stream around every kernel it launches.  rasp_kernel_times
+ * waits for the stream, then adds the elapsed time (ms) and the launch count
+ * of each kernel kind into ms[RASP_KERNEL_COUNT] and launches[RASP_KERNEL_COUNT]
+ * (either may be NULL) and forgets the recorded pairs.
+ */
+enum {
+    RASP_KERNEL_PACK = 0,          /* c0 construction                           */
+    RASP_KERNEL_PLAIN = 1,         /* one machine per lane step loop            */
+    RASP_KERNEL_PERSISTENT = 2,    /* work-queue step loop                      */
+    RASP_KERNEL_DIGEST = 3,        /* memory digests                            */
+    RASP_KERNEL_OTHER = 4,         /* checks, scans, copies, queue reset        */
+    RASP_KERNEL_COUNT = 5
+};
+enum { RASP_OPT_PROFILE = 7 };
+int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
+
 /* Device properties the context saw: compute units, LDS bytes per workgroup. */
 int rasp_device_info(rasp_ctx *ctx, int *compute_units, int *lds_bytes, int *wave_size);
 

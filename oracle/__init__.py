@@ -69,6 +69,8 @@ def _load():
     lib.or_c0.restype = ctypes.c_int
     lib.or_advance.argtypes = [ctypes.c_int, ctypes.c_int, u64, u64, ctypes.c_int] + [P] * 15
     lib.or_advance.restype = ctypes.c_int
+    lib.or_advance_mix.argtypes = [ctypes.c_int, ctypes.c_int, u64, u64, ctypes.c_int] + [P] * 16
+    lib.or_advance_mix.restype = ctypes.c_int
     lib.or_fnv1a64.argtypes = [P, u64]
     lib.or_fnv1a64.restype = u64
     lib.or_digest_batch.argtypes = [u64, P, P, P, P]
@@ -175,6 +177,26 @@ def advance(st: State, budget: int, threads: int = 1) -> None:
                         _p(st.Y), _p(st.y_off), _p(st.s))
     if rc != 0:
         raise ValueError("oracle: bad arguments to or_advance")
+
+
+MIX_NAMES = {1: "LOAD", 2: "ADD", 3: "SUB/MUL", 4: "STORE", 5: "JPOS/BNZ", 6: "READ",
+             7: "PRINT", 8: "JMP", 9: "PRINT appended"}
+
+
+def advance_mix(st: State, budget: int, threads: int = 1) -> np.ndarray:
+    """advance() that also returns the retired-opcode histogram (uint64[16]):
+    entry k (1..8) counts retired transitions with opcode k, entry 9 the PRINTs
+    that appended an output word."""
+    lib = _load()
+    mix = np.zeros(16, np.uint64)
+    rc = lib.or_advance_mix(st.isa, st.w, st.N, int(budget), int(threads),
+                            _p(st.i), _p(st.a), _p(st.u0), _p(st.y0), _p(st.steps), _p(st.status),
+                            _p(st.mem), _p(st.mem_off), _p(st.n),
+                            _p(st.tape), _p(st.t_off), _p(st.l),
+                            _p(st.Y), _p(st.y_off), _p(st.s), _p(mix))
+    if rc != 0:
+        raise ValueError("oracle: bad arguments to or_advance_mix")
+    return mix
 
 
 def run(batch, budget: int, w: int = 32, threads: int = 1) -> State:

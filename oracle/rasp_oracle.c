@@ -161,7 +161,8 @@ typedef struct {
 /* Advance one machine by at most `budget` transitions.  Returns the number of
  * transitions applied; *halted says whether the final configuration is a fixed
  * point. */
-static uint64_t run_one(int isa, int w, vm_t *v, uint64_t budget, int *halted)
+static uint64_t run_one(int isa, int w, vm_t *v, uint64_t budget, int *halted,
+                        uint64_t *hist)
 {
     uint64_t t = 0;
     for (;;) {
@@ -217,6 +218,10 @@ static uint64_t run_one(int isa, int w, vm_t *v, uint64_t budget, int *halted)
         v->i = ni; v->a = na; v->u0 = nu0; v->y0 = ny0;
         if (mw) v->M[maddr] = (int32_t)mval;
         if (yw) v->Y[yidx] = (int32_t)yval;
+        if (hist) {                      /* retired opcode, and appended outputs */
+            hist[kind] += 1;
+            hist[9] += (uint64_t)yw;
+        }
         ++t;
     }
 }
@@ -257,6 +262,7 @@ int or_c0(int w, uint64_t N,
 
 typedef struct {
     int isa, w; uint64_t N, budget; int stride, first;
+    uint64_t hist[16]; int count;
     int32_t *ri, *ra; uint32_t *ru0, *ry0; uint64_t *steps; uint8_t *status;
     int32_t *mem; const uint64_t *mem_off; const uint32_t *n;
     const int32_t *T; const uint64_t *t_off; const uint32_t *l;
@@ -273,7 +279,8 @@ static void *advance_stripe(void *arg)
         m.T = jb->T + jb->t_off[v]; m.l = jb->l[v]; m.u0 = jb->ru0[v];
         m.Y = jb->Y + jb->y_off[v]; m.s = jb->s[v]; m.y0 = jb->ry0[v];
         int halted = 0;
-        uint64_t t = run_one(jb->isa, jb->w, &m, jb->budget, &halted);
+        uint64_t t = run_one(jb->isa, jb->w, &m, jb->budget, &halted,
+                             jb->count ? jb->hist : NULL);
         jb->ri[v] = (int32_t)m.i; jb->ra[v] = (int32_t)m.a;
         jb->ru0[v] = (uint32_t)m.u0; jb->ry0[v] = (uint32_t)m.y0;
         jb->steps[v] += t;
@@ -290,12 +297,37 @@ static void *advance_stripe(void *arg)
  * as "final configuration is a fixed point".  Every machine must satisfy
  * u0 <= l and y0 <= s.  Returns 0, or -1 on bad arguments.
  */
+int or_advance_mix(int isa, int w, uint64_t N, uint64_t budget, int threads,
+                   int32_t *ri, int32_t *ra, uint32_t *ru0, uint32_t *ry0,
+                   uint64_t *steps, uint8_t *status,
+                   int32_t *mem, const uint64_t *mem_off, const uint32_t *n,
+                   const int32_t *T, const uint64_t *t_off, const uint32_t *l,
+                   int32_t *Y, const uint64_t *y_off, const uint32_t *s,
+                   uint64_t *mix);
+
 int or_advance(int isa, int w, uint64_t N, uint64_t budget, int threads,
                int32_t *ri, int32_t *ra, uint32_t *ru0, uint32_t *ry0,
                uint64_t *steps, uint8_t *status,
                int32_t *mem, const uint64_t *mem_off, const uint32_t *n,
                const int32_t *T, const uint64_t *t_off, const uint32_t *l,
                int32_t *Y, const uint64_t *y_off, const uint32_t *s)
+{
+    return or_advance_mix(isa, w, N, budget, threads, ri, ra, ru0, ry0, steps, status,
+                          mem, mem_off, n, T, t_off, l, Y, y_off, s, NULL);
+}
+
+/*
+ * or_advance_mix: or_advance that also adds, into mix[16] (when not NULL), the
+ * number of retired transitions per opcode (mix[1..8]; the stuck kinds never
+ * retire) and in mix[9] the number of PRINTs that appended an output word.
+ */
+int or_advance_mix(int isa, int w, uint64_t N, uint64_t budget, int threads,
+                   int32_t *ri, int32_t *ra, uint32_t *ru0, uint32_t *ry0,
+                   uint64_t *steps, uint8_t *status,
+                   int32_t *mem, const uint64_t *mem_off, const uint32_t *n,
+                   const int32_t *T, const uint64_t *t_off, const uint32_t *l,
+                   int32_t *Y, const uint64_t *y_off, const uint32_t *s,
+                   uint64_t *mix)
 {
     if (w < 2 || w > 32 || (isa != OR_ISA_WORD && isa != OR_ISA_CLASSIC)) return -1;
     for (uint64_t v = 0; v < N; ++v)
@@ -308,13 +340,14 @@ int or_advance(int isa, int w, uint64_t N, uint64_t budget, int threads,
     for (int t = 0; t < threads; ++t) {
         job_t *jb = &jobs[t];
         jb->isa = isa; jb->w = w; jb->N = N; jb->budget = budget;
-        jb->stride = threads; jb->first = t;
+        jb->stride = threads; jb->first = t; jb->count = (mix != NULL);
         jb->ri = ri; jb->ra = ra; jb->ru0 = ru0; jb->ry0 = ry0;
         jb->steps = steps; jb->status = status;
         jb->mem = mem; jb->mem_off = mem_off; jb->n = n;
         jb->T = T; jb->t_off = t_off; jb->l = l;
         jb->Y = Y; jb->y_off = y_off; jb->s = s;
     }
+    /* calloc zeroed every jobs[t].hist; run_one counts only when asked */
     if (threads == 1) {
         advance_stripe(&jobs[0]);
     } else {
@@ -326,6 +359,9 @@ int or_advance(int isa, int w, uint64_t N, uint64_t budget, int threads,
         for (int t = 0; t < started; ++t) pthread_join(tids[t], NULL);
         for (int t = started; t < threads; ++t) advance_stripe(&jobs[t]);
     }
+    if (mix)
+        for (int t = 0; t < threads; ++t)
+            for (int k = 0; k < 16; ++k) mix[k] += jobs[t].hist[k];
     free(jobs); free(tids);
     return 0;
 }

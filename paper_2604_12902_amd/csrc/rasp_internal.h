@@ -73,7 +73,7 @@ hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
                          const uint32_t *mem_words, uint32_t def_mem,
                          const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
                          uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
-                         uint64_t *n_pad, uint32_t *err, hipStream_t st);
+                         uint64_t *n_pad, uint32_t *err, uint32_t *max_n, hipStream_t st);
 hipError_t launch_scan_u64(const uint64_t *in, uint64_t *out_excl, uint64_t N,
                            uint64_t *block_sums, uint64_t *total, hipStream_t st);
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out_excl, uint64_t N,
@@ -87,7 +87,7 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap,
                         uint32_t isa, uint32_t *surv, QueueState *q, hipStream_t st);
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
                              uint32_t already, uint32_t isa, uint32_t epoch, uint32_t lds_words,
-                             uint32_t waves_per_block, uint32_t blocks,
+                             uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
                              QueueState *q, hipStream_t st);
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
 hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st);

@@ -27,62 +27,89 @@ namespace rasp {
 // circular addressing
 // ---------------------------------------------------------------------------
 
-__device__ __noinline__ uint32_t cmod_slow(int32_t v, uint32_t n)
-{
-    const int32_t r = v % static_cast<int32_t>(n);          // n <= 2^30
-    return static_cast<uint32_t>(r < 0 ? r + static_cast<int32_t>(n) : r);
-}
-
+// Euclidean remainder of a signed word by n (1 <= n <= 2^30); the common case
+// of an in-range word costs one compare.
 __device__ __forceinline__ uint32_t cmod(int32_t v, uint32_t n)
 {
-    return (static_cast<uint32_t>(v) < n) ? static_cast<uint32_t>(v) : cmod_slow(v, n);
+    if (static_cast<uint32_t>(v) < n) return static_cast<uint32_t>(v);
+    if ((n & (n - 1u)) == 0u) return static_cast<uint32_t>(v) & (n - 1u);
+    const int32_t r = v % static_cast<int32_t>(n);
+    return static_cast<uint32_t>(r < 0 ? r + static_cast<int32_t>(n) : r);
 }
 
 // position of the operand word (i + 1) mod n, given p = i mod n
 __device__ __forceinline__ uint32_t operand_pos(int32_t i, uint32_t p, uint32_t n)
 {
-    if (i == INT32_MAX) return cmod(INT32_MIN, n);          // i + 1 wraps
     const uint32_t q = p + 1u;
-    return q == n ? 0u : q;
+    uint32_t r = q == n ? 0u : q;
+    if (i == INT32_MAX) r = cmod(INT32_MIN, n);             // i + 1 wraps
+    return r;
 }
 
 // position of i + 2 (wrapping) given p = i mod n
 __device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t n)
 {
-    if (i > INT32_MAX - 2)
-        return cmod(static_cast<int32_t>(static_cast<uint32_t>(i) + 2u), n);
     uint32_t q = p + 2u;
     if (q >= n) q -= n;
     if (q >= n) q -= n;                                     // n == 1
+    if (i > INT32_MAX - 2) q = cmod(static_cast<int32_t>(static_cast<uint32_t>(i) + 2u), n);
     return q;
 }
 
 // ---------------------------------------------------------------------------
-// memory accessors
+// memory accessors.  kLds: every word of the machine is in its LDS slot, so
+// the data word is read unconditionally and a store that does not happen is
+// redirected to the slot's spare word (no branch).  Otherwise reads and
+// stores that would touch HBM are predicated.
 // ---------------------------------------------------------------------------
 
+extern __shared__ int32_t rasp_lds[];
+
 struct GlobalMem {                       // every word in HBM
+    static constexpr bool kLds = false;
     int32_t *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
-    __device__ __forceinline__ void st(uint32_t k, int32_t v) const { M[k] = v; }
+    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
+    {
+        int32_t v = 0;
+        if (need) v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const { if (en) M[k] = v; }
 };
 
-struct StagedMem {                       // words [0, P) in the lane's LDS slot
-    int32_t *L;
-    int32_t *M;
-    uint32_t P;
-    __device__ __forceinline__ int32_t ld(uint32_t k) const { return k < P ? L[k] : M[k]; }
-    __device__ __forceinline__ void st(uint32_t k, int32_t v) const
+struct LdsMem {                          // whole memory in the lane's LDS slot (n <= P)
+    static constexpr bool kLds = true;
+    uint32_t base;                       // word index of the slot in rasp_lds
+    uint32_t spare;                      // word index of the slot's spare word
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
+    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool) const { return rasp_lds[base + k]; }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
     {
-        if (k < P) L[k] = v; else M[k] = v;
+        rasp_lds[en ? base + k : spare] = v;
     }
 };
 
-struct C0Mem {                           // c0 read straight from the packed program
-    const int32_t *P;
-    uint32_t plen;
-    __device__ __forceinline__ int32_t ld(uint32_t k) const { return k < plen ? P[k] : 0; }
-    __device__ __forceinline__ void st(uint32_t, int32_t) const {}
+struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
+    static constexpr bool kLds = false;
+    uint32_t base, P;
+    int32_t *M;
+    __device__ __forceinline__ int32_t ld(uint32_t k) const
+    {
+        int32_t v;
+        if (k < P) v = rasp_lds[base + k]; else v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
+    {
+        int32_t v = 0;
+        if (k < P) v = rasp_lds[base + k]; else if (need) v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
+    {
+        if (en) { if (k < P) rasp_lds[base + k] = v; else M[k] = v; }
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -97,20 +124,26 @@ struct Regs {
 };
 
 // Advance one machine by at most `limit` transitions.  Returns the number
-// applied; `halted` says whether the machine now sits on a fixed point.
+// applied; `halted` says whether the machine now sits on a fixed point;
+// `wrote` is set when a transition stored into memory.
+//
+// Software-pipelined: the words of the next instruction are loaded together
+// with the data word of the current one (after the current store, so that a
+// program that rewrites its next instruction sees the new word), leaving one
+// memory round trip per transition.  The common case -- operand word already
+// in [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code;
+// everything else takes one branch that lanes skip when none needs it.
 template <int ISA, class Mem>
 __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
                                                 const int32_t *__restrict__ T,
                                                 int32_t *__restrict__ Y,
-                                                uint32_t limit, bool &halted)
+                                                uint32_t limit, bool &halted, bool &wrote)
 {
     uint32_t t = 0;
-    halted = false;
+    int32_t o = mem.ld(r.p);
+    int32_t j = mem.ld(operand_pos(r.i, r.p, r.n));
     for (;;) {
-        const int32_t o = mem.ld(r.p);
-        const int32_t j = mem.ld(operand_pos(r.i, r.p, r.n));
         const uint32_t op = static_cast<uint32_t>(o);
-
         bool is_ld, is_add, is_sub, is_mul, is_sto, is_rd, is_pr, taken, valid;
         is_ld = op == 1u;
         is_add = op == 2u;
@@ -131,28 +164,44 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
         const bool rd_ok = is_rd & (r.u0 < r.ell);
         const bool fixed = !valid | (is_rd & !rd_ok) | (taken & (j == r.i));
         if (fixed) { halted = true; break; }
-        if (t == limit) break;
+        if (t == limit) { halted = false; break; }
 
-        const uint32_t jj = cmod(j, r.n);
-        int32_t d = 0;
-        if (is_add | is_sub | is_mul | is_pr) d = mem.ld(jj);
-        if (is_sto) mem.st(jj, r.a);
-        if (rd_ok) { mem.st(jj, T[r.u0]); r.u0 += 1u; }
-        if (is_pr & (r.y0 < r.s)) { Y[r.y0] = d; r.y0 += 1u; }
+        // positions: data word jj = j mod n, next instruction np, its operand nq
+        uint32_t jj = static_cast<uint32_t>(j);
+        uint32_t seq = r.p + 2u;
+        seq = seq >= r.n ? seq - r.n : seq;
+        const bool rare = (static_cast<uint32_t>(j) >= r.n) | (r.i >= INT32_MAX - 3) | (r.n < 2u);
+        if (rare) {
+            jj = cmod(j, r.n);
+            seq = advance_pos(r.i, r.p, r.n);
+        }
+        const int32_t ni = taken ? j : static_cast<int32_t>(static_cast<uint32_t>(r.i) + 2u);
+        const uint32_t np = taken ? jj : seq;
+        uint32_t nq = np + 1u;
+        nq = nq == r.n ? 0u : nq;
+        if (rare) nq = operand_pos(ni, np, r.n);
+
+        const bool st_en = is_sto | rd_ok;
+        int32_t w = r.a;
+        if (rd_ok) w = T[r.u0];
+        mem.st(jj, w, st_en);
+        wrote |= st_en;
+        r.u0 += rd_ok ? 1u : 0u;
+        const int32_t d = mem.ld_data(jj, is_add | is_sub | is_mul | is_pr);
+        const int32_t jcur = j;
+        o = mem.ld(np);
+        j = mem.ld(nq);
+
         const uint32_t ua = static_cast<uint32_t>(r.a), ud = static_cast<uint32_t>(d);
         uint32_t na = ua;
-        if (is_ld) na = static_cast<uint32_t>(j);
-        if (is_add) na = ua + ud;
-        if (is_sub) na = ua - ud;
-        if (is_mul) na = ua * ud;
+        if (ISA == 1) na = is_sub ? ua - ud : na;
+        else na = is_mul ? ua * ud : na;
+        na = is_add ? ua + ud : na;
+        na = is_ld ? static_cast<uint32_t>(jcur) : na;
         r.a = static_cast<int32_t>(na);
-        if (taken) {
-            r.i = j;
-            r.p = jj;
-        } else {
-            r.p = advance_pos(r.i, r.p, r.n);
-            r.i = static_cast<int32_t>(static_cast<uint32_t>(r.i) + 2u);
-        }
+        if (is_pr & (r.y0 < r.s)) { Y[r.y0] = d; r.y0 += 1u; }
+        r.i = ni;
+        r.p = np;
         ++t;
     }
     return t;
@@ -169,11 +218,25 @@ __device__ __forceinline__ int batch_of(const BatchTable *tab, uint64_t g)
 }
 
 // ---------------------------------------------------------------------------
-// K1: pack c0 (Sec. 2.1): M = P 0^(n-2m), T = x 0^(l-|x|), Y = 0^s, scalars 0
-// One wave per machine, grid-stride; status = is c0 a fixed point.
+// K1: pack c0 (Sec. 2.1): M = P 0^(n-2m), T = x 0^(l-|x|), Y = 0^s, scalars 0.
+// One wave per 64 consecutive machines: the scalars and shapes are read and
+// written coalesced (lane = machine); then the wave walks its 64 machines and
+// copies each memory slice with 16-byte accesses (64 lanes x 4 words).
+// status is written RUNNING here; the host marks it stale and the first run
+// (or a probe) computes whether c0 is already a fixed point.
 // ---------------------------------------------------------------------------
 
-template <int ISA>
+__device__ __forceinline__ uint32_t bcast(uint32_t x, uint32_t L)
+{
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), static_cast<int>(L)));
+}
+
+__device__ __forceinline__ uint64_t bcast64(uint64_t x, uint32_t L)
+{
+    return (static_cast<uint64_t>(bcast(static_cast<uint32_t>(x >> 32), L)) << 32) |
+           bcast(static_cast<uint32_t>(x), L);
+}
+
 __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restrict__ prog,
                                               const uint64_t *__restrict__ prog_off,
                                               const int32_t *__restrict__ tape,
@@ -182,25 +245,42 @@ __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restr
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t wave = (static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = (static_cast<uint64_t>(gridDim.x) * blockDim.x) / kWave;
-    for (uint64_t v = wave; v < b.N; v += nwaves) {
-        const uint64_t p0 = prog_off[v];
-        const uint32_t plen = static_cast<uint32_t>(prog_off[v + 1] - p0);
-        const uint64_t t0 = tape_off[v];
-        const uint32_t tlen = static_cast<uint32_t>(tape_off[v + 1] - t0);
-        const uint32_t n = b.n[v], ell = b.ell[v], s = b.s[v];
-        int32_t *M = b.M + b.mem_off[v];
-        int32_t *T = b.T + b.t_off[v];
-        int32_t *Y = b.Y + b.y_off[v];
-        for (uint32_t k = lane; k < n; k += kWave) M[k] = k < plen ? prog[p0 + k] : 0;
-        for (uint32_t k = lane; k < ell; k += kWave) T[k] = k < tlen ? tape[t0 + k] : 0;
-        for (uint32_t k = lane; k < s; k += kWave) Y[k] = 0;
-        if (lane == 0) {
-            Regs r{0, 0, 0, 0, 0, n, ell, s};
-            C0Mem c0{prog + p0, plen};
-            bool halted;
-            run_machine<ISA>(c0, r, T, Y, 0u, halted);
-            b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0;
-            b.status[v] = halted ? 1 : 0;
+    for (uint64_t g = wave * kWave; g < b.N; g += nwaves * kWave) {
+        const uint64_t v = g + lane;
+        uint64_t p0 = 0, t0 = 0, mo = 0, to = 0, yo = 0;
+        uint32_t plen = 0, tlen = 0, n = 0, ell = 0, s = 0;
+        if (v < b.N) {
+            p0 = prog_off[v];
+            plen = static_cast<uint32_t>(prog_off[v + 1] - p0);
+            t0 = tape_off[v];
+            tlen = static_cast<uint32_t>(tape_off[v + 1] - t0);
+            n = b.n[v]; ell = b.ell[v]; s = b.s[v];
+            mo = b.mem_off[v]; to = b.t_off[v]; yo = b.y_off[v];
+            b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0; b.status[v] = 0;
+        }
+        const uint32_t cnt = static_cast<uint32_t>(b.N - g < kWave ? b.N - g : kWave);
+        for (uint32_t L = 0; L < cnt; ++L) {
+            const uint64_t P0 = bcast64(p0, L), MO = bcast64(mo, L);
+            const uint32_t PL = bcast(plen, L), NN = bcast(n, L);
+            const int32_t *src = prog + P0;
+            int32_t *M = b.M + MO;
+            const bool aligned = (P0 & 3u) == 0;
+            for (uint32_t k = 4 * lane; k < NN; k += 4 * kWave) {
+                int4 w;
+                if (aligned && k + 4 <= PL) {
+                    w = *reinterpret_cast<const int4 *>(src + k);
+                } else {
+                    w.x = k < PL ? src[k] : 0;
+                    w.y = k + 1 < PL ? src[k + 1] : 0;
+                    w.z = k + 2 < PL ? src[k + 2] : 0;
+                    w.w = k + 3 < PL ? src[k + 3] : 0;
+                }
+                *reinterpret_cast<int4 *>(M + k) = w;      // slices are padded to 4 words
+            }
+            const uint64_t T0 = bcast64(t0, L), TO = bcast64(to, L), YO = bcast64(yo, L);
+            const uint32_t TL = bcast(tlen, L), EL = bcast(ell, L), SS = bcast(s, L);
+            for (uint32_t k = lane; k < EL; k += kWave) b.T[TO + k] = k < TL ? tape[T0 + k] : 0;
+            for (uint32_t k = lane; k < SS; k += kWave) b.Y[YO + k] = 0;
         }
     }
 }
@@ -208,13 +288,9 @@ __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restr
 hipError_t launch_pack(DevBatch b, const int32_t *prog, const uint64_t *prog_off,
                        const int32_t *tape, const uint64_t *tape_off, hipStream_t st)
 {
-    const uint64_t waves = b.N;
-    uint64_t blocks = (waves + 3) / 4;
-    if (blocks > 65536 * 4) blocks = 65536 * 4;
-    if (b.isa == 1)
-        k_pack<1><<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st>>>(b, prog, prog_off, tape, tape_off);
-    else
-        k_pack<0><<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st>>>(b, prog, prog_off, tape, tape_off);
+    uint64_t blocks = (b.N + 255) / 256;                   // 4 waves x 64 machines
+    if (blocks > 65536) blocks = 65536;
+    k_pack<<<dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st>>>(b, prog, prog_off, tape, tape_off);
     return hipGetLastError();
 }
 
@@ -229,8 +305,8 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
     r.p = cmod(r.i, r.n);
     GlobalMem g{b.M + b.mem_off[v]};
-    bool halted;
-    run_machine<ISA>(g, r, b.T + b.t_off[v], b.Y + b.y_off[v], 0u, halted);
+    bool halted, wrote = false;
+    run_machine<ISA>(g, r, b.T + b.t_off[v], b.Y + b.y_off[v], 0u, halted, wrote);
     b.status[v] = halted ? 1 : 0;
 }
 
@@ -256,7 +332,6 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
 {
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     bool survive = false;
-    unsigned long long retired = 0;
     if (g < total) {
         const int k = batch_of(tab, g);
         const DevBatch &b = tab->b[k];
@@ -269,12 +344,14 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             r.p = cmod(r.i, r.n);
             const uint32_t limit = cap < budget ? cap : budget;
             GlobalMem m{b.M + b.mem_off[v]};
-            bool halted;
-            const uint32_t t = run_machine<ISA>(m, r, b.T + b.t_off[v], b.Y + b.y_off[v], limit, halted);
-            b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
-            b.steps[v] += t;
-            b.status[v] = halted ? 1 : 0;
-            retired = t;
+            bool halted, wrote = false;
+            const uint32_t t = run_machine<ISA>(m, r, b.T + b.t_off[v], b.Y + b.y_off[v], limit,
+                                                halted, wrote);
+            if (t) {
+                b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
+                b.steps[v] += t;
+            }
+            if (halted) b.status[v] = 1;
             survive = !halted && t == limit && limit < budget;
         }
     }
@@ -293,7 +370,6 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             }
         }
     }
-    (void)retired;
 }
 
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uint32_t isa,
@@ -310,28 +386,30 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uin
 // queue (one agent-scope atomic per wave refill), run each lane's machine for
 // at most `epoch` transitions between refill points, write back machines
 // that halted or spent their budget, and refill exactly those lanes (wave
-// ballot + popcount prefix ranks).  Memory words [0, P) of each live machine
-// are staged in the lane's LDS slot (P = lds_words; 0 keeps everything in
-// HBM); staging and write-back are cooperative 64-lane copies.
-// Work item k is machine work[k] of the launch (or machine k when work is
-// null); machines have already applied `already` transitions this run.
+// ballot + popcount prefix ranks).
+// MODE 0: memory in HBM.  MODE 1: each live machine's whole memory is staged
+// in its lane's LDS slot of P words (every n <= P).  MODE 2: words [0, P) in
+// LDS, the rest in HBM.  Staging and write-back are cooperative 16-byte
+// copies by the whole wave; only machines that stored into LDS are written
+// back.  Work item k is machine work[k] of the launch (or machine k when work
+// is null); machines have already applied `already` transitions this run.
 // ---------------------------------------------------------------------------
 
-template <int ISA, bool STAGED>
+template <int ISA, int MODE>
 __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict__ tab,
                                                     uint64_t total,
                                                     const uint32_t *__restrict__ work,
                                                     uint32_t already, uint32_t epoch,
                                                     uint32_t P, QueueState *__restrict__ q)
 {
-    extern __shared__ int32_t lds[];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = threadIdx.x / kWave;
-    if (work != nullptr) total = q->survivors;           // written by the plain pass
-    int32_t *slot = STAGED ? lds + static_cast<size_t>(wib * kWave + lane) * P : nullptr;
+    const uint32_t SP = P + 4u;                            // slot stride: P words + spare
+    const uint32_t wave_base = wib * kWave * SP;           // word index of lane 0's slot
+    const uint32_t slot = wave_base + lane * SP;
+    if (work != nullptr) total = q->survivors;             // written by the plain pass
 
-    bool has = false;
-    bool exhausted = false;
+    bool has = false, exhausted = false, wrote = false;
     Regs r{};
     int32_t *M = nullptr;
     const int32_t *T = nullptr;
@@ -339,7 +417,6 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
     uint32_t done = 0, limit = 0;
     const DevBatch *bp = nullptr;
     uint64_t v = 0;
-    bool dirty = false;
 
     for (;;) {
         // ---- refill idle lanes from the queue ----
@@ -372,7 +449,7 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                         Y = bp->Y + bp->y_off[v];
                         done = 0;
                         limit = budget - already;
-                        dirty = false;
+                        wrote = false;
                         has = true;
                         fresh = true;
                     }
@@ -385,19 +462,17 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             continue;
         }
         // ---- stage the fresh machines' low memory words into LDS ----
-        if (STAGED && fresh_mask) {
+        if (MODE != 0) {
             uint64_t m = fresh_mask;
             while (m) {
-                const int L = __ffsll(static_cast<unsigned long long>(m)) - 1;
+                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
                 m &= m - 1;
-                const uint64_t mp = reinterpret_cast<uint64_t>(M);
-                const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp), L);
-                const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp >> 32), L);
-                const uint32_t nL = __builtin_amdgcn_readlane(r.n, L);
-                const int32_t *src = reinterpret_cast<const int32_t *>((static_cast<uint64_t>(hi) << 32) | lo);
-                int32_t *dst = lds + static_cast<size_t>(wib * kWave + L) * P;
+                const int32_t *src = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L));
+                const uint32_t nL = bcast(r.n, L);
                 const uint32_t cnt = nL < P ? nL : P;
-                for (uint32_t k = lane; k < cnt; k += kWave) dst[k] = src[k];
+                const uint32_t dst = wave_base + L * SP;
+                for (uint32_t k = 4 * lane; k < cnt; k += 4 * kWave)
+                    *reinterpret_cast<int4 *>(&rasp_lds[dst + k]) = *reinterpret_cast<const int4 *>(src + k);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -409,41 +484,42 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             if (lim > epoch) lim = epoch;
             bool halted;
             uint32_t t;
-            if (STAGED) {
-                StagedMem sm{slot, M, P};
-                t = run_machine<ISA>(sm, r, T, Y, lim, halted);
-                // conservatively dirty once anything ran: a store may have hit LDS
-                dirty |= (t != 0);
+            if (MODE == 1) {
+                LdsMem mm{slot, slot + P};
+                t = run_machine<ISA>(mm, r, T, Y, lim, halted, wrote);
+            } else if (MODE == 2) {
+                SplitMem mm{slot, P, M};
+                t = run_machine<ISA>(mm, r, T, Y, lim, halted, wrote);
             } else {
-                GlobalMem gm{M};
-                t = run_machine<ISA>(gm, r, T, Y, lim, halted);
+                GlobalMem mm{M};
+                t = run_machine<ISA>(mm, r, T, Y, lim, halted, wrote);
             }
             done += t;
             if (halted || done == limit) {
-                bp->i[v] = r.i; bp->a[v] = r.a; bp->u0[v] = r.u0; bp->y0[v] = r.y0;
-                bp->steps[v] += done;
-                bp->status[v] = halted ? 1 : 0;
+                if (done) {
+                    bp->i[v] = r.i; bp->a[v] = r.a; bp->u0[v] = r.u0; bp->y0[v] = r.y0;
+                    bp->steps[v] += done;
+                }
+                if (halted) bp->status[v] = 1;
                 finish = true;
             }
         }
-        // ---- write back staged words of finished machines ----
-        if (STAGED) {
-            uint64_t m = __ballot(finish && dirty);
+        // ---- write back staged words of finished machines that stored ----
+        if (MODE != 0) {
+            uint64_t m = __ballot(finish && wrote);
             if (m) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
             while (m) {
-                const int L = __ffsll(static_cast<unsigned long long>(m)) - 1;
+                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
                 m &= m - 1;
-                const uint64_t mp = reinterpret_cast<uint64_t>(M);
-                const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp), L);
-                const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(mp >> 32), L);
-                const uint32_t nL = __builtin_amdgcn_readlane(r.n, L);
-                int32_t *dst = reinterpret_cast<int32_t *>((static_cast<uint64_t>(hi) << 32) | lo);
-                const int32_t *src = lds + static_cast<size_t>(wib * kWave + L) * P;
+                int32_t *dstp = reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L));
+                const uint32_t nL = bcast(r.n, L);
                 const uint32_t cnt = nL < P ? nL : P;
-                for (uint32_t k = lane; k < cnt; k += kWave) dst[k] = src[k];
+                const uint32_t src = wave_base + L * SP;
+                for (uint32_t k = 4 * lane; k < cnt; k += 4 * kWave)
+                    *reinterpret_cast<int4 *>(dstp + k) = *reinterpret_cast<const int4 *>(&rasp_lds[src + k]);
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -452,32 +528,38 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
     }
 }
 
+template <int MODE>
+static void set_lds_attr()
+{
+    static bool done = false;
+    if (done) return;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<1, MODE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<0, MODE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    done = true;
+}
+
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
-                                uint32_t already, uint32_t isa, uint32_t epoch,
-                                uint32_t lds_words, uint32_t waves_per_block, uint32_t blocks,
-                                QueueState *q, hipStream_t st)
+                             uint32_t already, uint32_t isa, uint32_t epoch, uint32_t lds_words,
+                             uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
+                             QueueState *q, hipStream_t st)
 {
     const dim3 grid(blocks), block(waves_per_block * kWave);
-    const size_t shmem = static_cast<size_t>(waves_per_block) * kWave * lds_words * sizeof(int32_t);
-    if (lds_words > 0) {
-        static bool attr_set = false;
-        if (!attr_set) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<1, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<0, true>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            (void)hipGetLastError();
-            attr_set = true;
-        }
-        if (isa == 1)
-            k_persistent<1, true><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
-        else
-            k_persistent<0, true><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
+    const size_t shmem = static_cast<size_t>(waves_per_block) * kWave * (lds_words + 4) * sizeof(int32_t);
+    const int mode = lds_words == 0 ? 0 : (max_n <= lds_words ? 1 : 2);
+    if (mode == 1) {
+        set_lds_attr<1>();
+        if (isa == 1) k_persistent<1, 1><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
+        else k_persistent<0, 1><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
+    } else if (mode == 2) {
+        set_lds_attr<2>();
+        if (isa == 1) k_persistent<1, 2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
+        else k_persistent<0, 2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
     } else {
-        if (isa == 1)
-            k_persistent<1, false><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
-        else
-            k_persistent<0, false><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
+        if (isa == 1) k_persistent<1, 0><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
+        else k_persistent<0, 0><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
     }
     return hipGetLastError();
 }
@@ -555,10 +637,12 @@ __global__ __launch_bounds__(256) void k_shapes(const uint64_t *__restrict__ pro
                                                 const uint32_t *__restrict__ out_cap, uint32_t def_out,
                                                 uint64_t N, uint32_t *__restrict__ n_out,
                                                 uint32_t *__restrict__ ell_out, uint32_t *__restrict__ s_out,
-                                                uint64_t *__restrict__ n_pad, uint32_t *__restrict__ err)
+                                                uint64_t *__restrict__ n_pad, uint32_t *__restrict__ err,
+                                                uint32_t *__restrict__ max_n)
 {
-    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= N) return;
+    const uint64_t v0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool in = v0 < N;
+    const uint64_t v = in ? v0 : N - 1;                    // out-of-range lanes repeat the last machine
     uint32_t e = 0;
     const uint64_t p0 = prog_off[v], p1 = prog_off[v + 1];
     const uint64_t t0 = tape_off[v], t1 = tape_off[v + 1];
@@ -572,21 +656,47 @@ __global__ __launch_bounds__(256) void k_shapes(const uint64_t *__restrict__ pro
     if (plen > n) e |= kErrProgTooLong;
     if (tlen > ell || ell > 0x7fffffffull) e |= kErrTapeTooLong;
     if (s > 0x7fffffffu) e |= kErrMemSize;
-    n_out[v] = n;
-    ell_out[v] = static_cast<uint32_t>(ell);
-    s_out[v] = s;
-    n_pad[v] = (static_cast<uint64_t>(n) + 3ull) & ~3ull;
+    if (in) {
+        n_out[v] = n;
+        ell_out[v] = static_cast<uint32_t>(ell);
+        s_out[v] = s;
+        n_pad[v] = (static_cast<uint64_t>(n) + 3ull) & ~3ull;
+    }
     if (e) atomicOr(err, e);
+    (void)max_n;
+}
+
+// maximum of a u32 array: a fixed grid of 256 blocks, grid-stride, one
+// atomic per block
+__global__ __launch_bounds__(256) void k_max_u32(const uint32_t *__restrict__ in, uint64_t N,
+                                                 uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t wmax[256 / kWave];
+    uint32_t mx = 0;
+    for (uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < N;
+         v += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+        mx = max(mx, in[v]);
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), off)));
+    if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < static_cast<int>(blockDim.x / kWave); ++w) mx = max(mx, wmax[w]);
+        atomicMax(out, mx);
+    }
 }
 
 hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
                          const uint32_t *mem_words, uint32_t def_mem,
                          const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
                          uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
-                         uint64_t *n_pad, uint32_t *err, hipStream_t st)
+                         uint64_t *n_pad, uint32_t *err, uint32_t *max_n, hipStream_t st)
 {
     k_shapes<<<static_cast<unsigned>((N + 255) / 256), 256, 0, st>>>(
-        prog_off, tape_off, mem_words, def_mem, tape_cap, out_cap, def_out, N, n, ell, s, n_pad, err);
+        prog_off, tape_off, mem_words, def_mem, tape_cap, out_cap, def_out, N, n, ell, s, n_pad, err, max_n);
+    hipError_t e = hipGetLastError();
+    if (e) return e;
+    k_max_u32<<<256, 256, 0, st>>>(n, N, max_n);
     return hipGetLastError();
 }
 

@@ -20,6 +20,8 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kTableRing = 16;
+constexpr uint64_t kStageWords = 32ull << 20;    // host-load staging: program + input words per chunk
+constexpr uint64_t kStageVms = 1ull << 20;       // and machines per chunk
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -79,7 +81,9 @@ struct Batch {
     Alloc meta, words;
     uint64_t N = 0;
     uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
+    uint32_t max_n = 0;
     bool uniform_dense = false;          // every n a multiple of 4: padded == dense
+    bool status_stale = true;            // status not yet computed since the load
 };
 
 uint64_t meta_bytes(uint64_t N)
@@ -158,6 +162,11 @@ struct rasp_ctx {
     uint64_t work_cap = 0;
     uint32_t *err_host = nullptr;        // pinned: error word and totals
     uint64_t *tot_host = nullptr;
+    // kernel timing (RASP_OPT_PROFILE)
+    int64_t profile = 0;
+    struct Timed { int kind; hipEvent_t a, b; };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
@@ -219,12 +228,40 @@ Batch *find(rasp_ctx *c, rasp_batch b)
     return it == c->batches.end() ? nullptr : it->second.get();
 }
 
+hipEvent_t pooled_event(rasp_ctx *c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` (returning hipError_t) on the context stream, bracketed by timing
+// events when profiling is on.
+template <class F>
+hipError_t timed_launch(rasp_ctx *c, int kind, F fn)
+{
+    if (!c->profile) return fn();
+    hipEvent_t a = pooled_event(c), b = pooled_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, c->stream);
+    if (!e) e = fn();
+    if (!e) e = hipEventRecord(b, c->stream);
+    if (!e) c->timed.push_back({kind, a, b});
+    return e;
+}
+
 // Host-side checks of a descriptor with host arrays; fills shapes and totals.
 struct HostShapes {
     std::vector<uint32_t> n, ell, s;
     std::vector<uint64_t> mem_off, t_off, y_off;
     uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
     uint64_t prog_words = 0, tape_words = 0;
+    uint32_t max_n = 0;
     bool all_n_mult4 = true;
 };
 
@@ -252,6 +289,7 @@ int host_shapes(rasp_ctx *c, const rasp_batch_desc *d, HostShapes *h)
         h->mem_off[v] = h->sum_n_pad; h->t_off[v] = h->sum_ell; h->y_off[v] = h->sum_s;
         h->sum_n += n; h->sum_n_pad += (n + 3u) & ~3ull; h->sum_ell += ell; h->sum_s += s;
         if (n & 3u) h->all_n_mult4 = false;
+        h->max_n = std::max(h->max_n, n);
     }
     h->prog_words = d->prog_off[N] - d->prog_off[0];
     h->tape_words = d->tape_off[N] - d->tape_off[0];
@@ -304,38 +342,80 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         if (h.tape_words && !d->tape) { fail(c, RASP_E_INVAL, "tape is NULL"); return bail(RASP_E_INVAL); }
         B->sum_n = h.sum_n; B->sum_n_pad = h.sum_n_pad; B->sum_ell = h.sum_ell; B->sum_s = h.sum_s;
         B->uniform_dense = h.all_n_mult4;
-        const uint64_t sb = align_up(4 * h.prog_words, kAlign) + align_up(4 * h.tape_words, kAlign) +
-                            2 * align_up(8 * (N + 1), kAlign);
-        if (!arena_alloc(c, words_bytes(h.sum_n_pad, h.sum_ell, h.sum_s), &B->words) || !arena_alloc(c, sb, &staging)) {
+        B->max_n = h.max_n;
+        if (!arena_alloc(c, words_bytes(h.sum_n_pad, h.sum_ell, h.sum_s), &B->words)) {
             fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)h.sum_n);
             return bail(RASP_E_NOMEM);
         }
-        char *sp = at<char>(c, staging);
-        int32_t *pg = reinterpret_cast<int32_t *>(sp);
-        int32_t *tp = reinterpret_cast<int32_t *>(sp + align_up(4 * h.prog_words, kAlign));
-        uint64_t *po = reinterpret_cast<uint64_t *>(sp + align_up(4 * h.prog_words, kAlign) + align_up(4 * h.tape_words, kAlign));
-        uint64_t *to = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(po) + align_up(8 * (N + 1), kAlign));
-        // offsets rebased so that the staged arrays start at 0
-        std::vector<uint64_t> po_h(N + 1), to_h(N + 1);
-        for (uint64_t v = 0; v <= N; ++v) { po_h[v] = d->prog_off[v] - d->prog_off[0]; to_h[v] = d->tape_off[v] - d->tape_off[0]; }
+        carve_words(at<char>(c, B->words), B->sum_n_pad, B->sum_ell, &B->dev);
         auto H2D = [&](void *dst, const void *src, uint64_t bytes) {
             return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
         };
         hipError_t e = hipSuccess;
-        if (!e) e = H2D(pg, d->prog + d->prog_off[0], 4 * h.prog_words);
-        if (!e) e = H2D(tp, d->tape + d->tape_off[0], 4 * h.tape_words);
-        if (!e) e = H2D(po, po_h.data(), 8 * (N + 1));
-        if (!e) e = H2D(to, to_h.data(), 8 * (N + 1));
         if (!e) e = H2D(B->dev.n, h.n.data(), 4 * N);
         if (!e) e = H2D(B->dev.ell, h.ell.data(), 4 * N);
         if (!e) e = H2D(B->dev.s, h.s.data(), 4 * N);
         if (!e) e = H2D(B->dev.mem_off, h.mem_off.data(), 8 * N);
         if (!e) e = H2D(B->dev.t_off, h.t_off.data(), 8 * N);
         if (!e) e = H2D(B->dev.y_off, h.y_off.data(), 8 * N);
-        carve_words(at<char>(c, B->words), B->sum_n_pad, B->sum_ell, &B->dev);
-        if (!e) e = launch_pack(B->dev, pg, po, tp, to, st);
-        // the staged copies are read by the pack kernel; sync before releasing
-        if (!e) e = hipStreamSynchronize(st);
+        // programs and inputs go through a bounded staging buffer, a chunk of
+        // machines at a time; each chunk is packed from its staged copy
+        const uint64_t budget_words = std::max<uint64_t>(kStageWords, 0);
+        uint64_t max_chunk_words = 0;
+        {
+            uint64_t v0 = 0;
+            while (v0 < N) {
+                uint64_t v1 = v0, words = 0;
+                while (v1 < N) {
+                    const uint64_t w = (d->prog_off[v1 + 1] - d->prog_off[v1]) + (d->tape_off[v1 + 1] - d->tape_off[v1]);
+                    if (v1 > v0 && (words + w > budget_words || v1 - v0 >= kStageVms)) break;
+                    words += w;
+                    ++v1;
+                }
+                max_chunk_words = std::max(max_chunk_words, words);
+                v0 = v1;
+            }
+        }
+        const uint64_t sb = align_up(4 * max_chunk_words, kAlign) + 2 * align_up(8 * (std::min<uint64_t>(N, kStageVms) + 1), kAlign) + kAlign;
+        if (!e && !arena_alloc(c, sb, &staging)) {
+            fail(c, RASP_E_NOMEM, "arena cannot hold the load staging buffer");
+            return bail(RASP_E_NOMEM);
+        }
+        std::vector<uint64_t> po_h, to_h;
+        uint64_t v0 = 0;
+        while (!e && v0 < N) {
+            uint64_t v1 = v0, words = 0;
+            while (v1 < N) {
+                const uint64_t w = (d->prog_off[v1 + 1] - d->prog_off[v1]) + (d->tape_off[v1 + 1] - d->tape_off[v1]);
+                if (v1 > v0 && (words + w > budget_words || v1 - v0 >= kStageVms)) break;
+                words += w;
+                ++v1;
+            }
+            const uint64_t cn = v1 - v0;
+            const uint64_t pw = d->prog_off[v1] - d->prog_off[v0], tw = d->tape_off[v1] - d->tape_off[v0];
+            char *sp = at<char>(c, staging);
+            int32_t *pg = reinterpret_cast<int32_t *>(sp);
+            int32_t *tp = pg + pw;
+            uint64_t *po = reinterpret_cast<uint64_t *>(sp + align_up(4 * max_chunk_words, kAlign));
+            uint64_t *to = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(po) + align_up(8 * (std::min<uint64_t>(N, kStageVms) + 1), kAlign));
+            po_h.resize(cn + 1); to_h.resize(cn + 1);
+            for (uint64_t v = 0; v <= cn; ++v) {
+                po_h[v] = d->prog_off[v0 + v] - d->prog_off[v0];
+                to_h[v] = d->tape_off[v0 + v] - d->tape_off[v0] + pw;   // tape words follow the program words
+            }
+            if (!e) e = H2D(pg, d->prog + d->prog_off[v0], 4 * pw);
+            if (!e) e = H2D(tp, d->tape + d->tape_off[v0], 4 * tw);
+            if (!e) e = H2D(po, po_h.data(), 8 * (cn + 1));
+            if (!e) e = H2D(to, to_h.data(), 8 * (cn + 1));
+            DevBatch view = B->dev;
+            view.i += v0; view.a += v0; view.u0 += v0; view.y0 += v0; view.steps += v0; view.status += v0;
+            view.n += v0; view.ell += v0; view.s += v0; view.mem_off += v0; view.t_off += v0; view.y_off += v0;
+            view.N = cn;
+            if (!e) e = timed_launch(c, RASP_KERNEL_PACK, [&] { return launch_pack(view, pg, po, pg, to, st); });
+            // the staging buffer and the host offset vectors are reused: wait
+            if (!e) e = hipStreamSynchronize(st);
+            v0 = v1;
+        }
         if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         arena_free(c, &staging);
     } else {
@@ -350,12 +430,13 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         uint32_t *errw = reinterpret_cast<uint32_t *>(tots + 4);
         hipError_t e = hipMemsetAsync(tots, 0, kAlign, st);
         if (!e) e = launch_shapes(d->prog_off, d->tape_off, d->mem_words, d->default_mem_words, d->tape_cap,
-                                  d->out_cap, d->default_out_cap, N, B->dev.n, B->dev.ell, B->dev.s, n_pad, errw, st);
+                                  d->out_cap, d->default_out_cap, N, B->dev.n, B->dev.ell, B->dev.s, n_pad, errw,
+                                  errw + 1, st);
         if (!e) e = launch_scan_u64(n_pad, B->dev.mem_off, N, sums, &tots[0], st);
         if (!e) e = launch_scan_u32(B->dev.ell, B->dev.t_off, N, sums + align_up(8 * nsc, kAlign) / 8, &tots[1], st);
         if (!e) e = launch_scan_u32(B->dev.s, B->dev.y_off, N, sums + 2 * align_up(8 * nsc, kAlign) / 8, &tots[2], st);
         if (!e) e = launch_scan_u32(B->dev.n, n_pad, N, sums, &tots[3], st);   // dense total into tots[3]
-        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
         if (!e) e = hipStreamSynchronize(st);
         if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         uint32_t errbits;
@@ -365,6 +446,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
             return bail(RASP_E_INVAL);
         }
         B->sum_n_pad = c->tot_host[0]; B->sum_ell = c->tot_host[1]; B->sum_s = c->tot_host[2]; B->sum_n = c->tot_host[3];
+        std::memcpy(&B->max_n, reinterpret_cast<char *>(c->tot_host) + 36, 4);
         B->uniform_dense = (B->sum_n == B->sum_n_pad);
         if (!arena_alloc(c, words_bytes(B->sum_n_pad, B->sum_ell, B->sum_s), &B->words)) {
             fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)B->sum_n);
@@ -372,7 +454,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         }
         carve_words(at<char>(c, B->words), B->sum_n_pad, B->sum_ell, &B->dev);
         prog_dev = d->prog; tape_dev = d->tape; poff_dev = d->prog_off; toff_dev = d->tape_off;
-        e = launch_pack(B->dev, prog_dev, poff_dev, tape_dev, toff_dev, st);
+        e = timed_launch(c, RASP_KERNEL_PACK, [&] { return launch_pack(B->dev, prog_dev, poff_dev, tape_dev, toff_dev, st); });
         if (e) { fail(c, RASP_E_DEVICE, "pack: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         // scratch is only used by work queued before this point: stream order makes reuse safe
         arena_free(c, &staging);
@@ -420,8 +502,9 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     if (rc) return rc;
     std::memset(ht, 0, sizeof(BatchTable));
     uint64_t total = 0;
-    uint32_t maxb = 0;
+    uint32_t maxb = 0, max_n = 0;
     for (uint32_t t = 0; t < k; ++t) {
+        max_n = std::max(max_n, bs[t]->max_n);
         ht->b[t] = bs[t]->dev;
         ht->start[t] = total;
         ht->budget[t] = budgets[t];
@@ -432,16 +515,18 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     ht->count = k;
     if (total >= (1ull << 32)) return fail(c, RASP_E_INVAL, "too many machines in one launch");
     if (maxb == 0) return RASP_OK;
+    for (uint32_t t = 0; t < k; ++t)
+        if (budgets[t] > 0) bs[t]->status_stale = false;    // every run recomputes status
     hipStream_t st = c->stream;
     HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
     c->table_used[slot] = true;
-    HIPCHK(c, launch_zero_queue(c->queue, st));
+    HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_zero_queue(c->queue, st); }));
 
     int64_t sched = c->schedule;
     if (sched == RASP_SCHED_AUTO) sched = RASP_SCHED_PERSISTENT;
     if (sched == RASP_SCHED_PLAIN) {
-        HIPCHK(c, launch_plain(dt, total, maxb, isa, nullptr, c->queue, st));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, nullptr, c->queue, st); }));
         return RASP_OK;
     }
     // persistent: a first plain pass of `first_pass` steps retires the short
@@ -450,21 +535,23 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     // waves per block: as many (up to 4) as the LDS slots of one block allow
     uint32_t P = static_cast<uint32_t>(std::max<int64_t>(0, c->lds_words));
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
-    while (P && static_cast<uint64_t>(kWave) * P * 4 > lds) P >>= 1;
+    while (P && static_cast<uint64_t>(kWave) * (P + 4) * 4 > lds) P >>= 1;
     uint32_t wpb = 4;
-    while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * P * 4 > lds) wpb >>= 1;
+    while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * (P + 4) * 4 > lds) wpb >>= 1;
     const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
     const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
     const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
     if (cap > 0 && cap < maxb) {
         if ((rc = ensure_work(c, total))) return rc;
         uint32_t *work = at<uint32_t>(c, c->work);
-        HIPCHK(c, launch_plain(dt, total, cap, isa, work, c->queue, st));
-        HIPCHK(c, launch_persistent(dt, total, work, cap, isa, epoch, P, wpb, blocks, c->queue, st));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, cap, isa, work, c->queue, st); }));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
+            return launch_persistent(dt, total, work, cap, isa, epoch, P, max_n, wpb, blocks, c->queue, st); }));
     } else if (cap >= maxb) {
-        HIPCHK(c, launch_plain(dt, total, maxb, isa, nullptr, c->queue, st));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, nullptr, c->queue, st); }));
     } else {
-        HIPCHK(c, launch_persistent(dt, total, nullptr, 0, isa, epoch, P, wpb, blocks, c->queue, st));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
+            return launch_persistent(dt, total, nullptr, 0, isa, epoch, P, max_n, wpb, blocks, c->queue, st); }));
     }
     return RASP_OK;
 }
@@ -543,6 +630,8 @@ int rasp_destroy(rasp_ctx *c)
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < kTableRing; ++k)
         if (c->table_ev[k]) (void)hipEventDestroy(c->table_ev[k]);
+    for (auto &t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->host_tables) (void)hipHostFree(c->host_tables);
     if (c->tot_host) (void)hipHostFree(c->tot_host);
     if (c->own_arena && c->arena) (void)hipFree(c->arena);
@@ -648,6 +737,7 @@ int rasp_load_state(rasp_ctx *c, const rasp_batch_desc *d, const rasp_outputs *s
     if (!e) e = hipMemsetAsync(derr, 0, 4, st);
     if (!e) e = launch_check_state(b.dev, derr, st);
     if (!e) e = launch_probe(b.dev, st);
+    if (!e) b.status_stale = false;
     if (!e) e = hipMemcpyAsync(errw, derr, 4, hipMemcpyDeviceToHost, st);
     if (!e) e = hipStreamSynchronize(st);
     if (e) { fail(c, RASP_E_DEVICE, "state load: %s", hipGetErrorString(e)); return undo(RASP_E_DEVICE); }
@@ -724,6 +814,10 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
     hipStream_t st = c->stream;
     const hipMemcpyKind kind = (o->flags & RASP_OUT_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const uint64_t N = b->N;
+    if (o->status && b->status_stale) {
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_probe(b->dev, st); }));
+        b->status_stale = false;
+    }
     if (o->status) HIPCHK(c, hipMemcpyAsync(o->status, b->dev.status, N, kind, st));
     if (o->steps) HIPCHK(c, hipMemcpyAsync(o->steps, b->dev.steps, 8 * N, kind, st));
     if (o->i) HIPCHK(c, hipMemcpyAsync(o->i, b->dev.i, 4 * N, kind, st));
@@ -734,10 +828,10 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
     Alloc tmp;
     if (o->mem_digest) {
         if (kind == hipMemcpyDeviceToDevice) {
-            HIPCHK(c, launch_digest(b->dev, o->mem_digest, st));
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_DIGEST, [&] { return launch_digest(b->dev, o->mem_digest, st); }));
         } else {
             if (!arena_alloc(c, 8 * N, &tmp)) return fail(c, RASP_E_NOMEM, "arena cannot hold digests");
-            HIPCHK(c, launch_digest(b->dev, at<uint64_t>(c, tmp), st));
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_DIGEST, [&] { return launch_digest(b->dev, at<uint64_t>(c, tmp), st); }));
             HIPCHK(c, hipMemcpyAsync(o->mem_digest, at<uint64_t>(c, tmp), 8 * N, kind, st));
             HIPCHK(c, hipStreamSynchronize(st));
             arena_free(c, &tmp);
@@ -815,7 +909,8 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
         if (value < 1 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "epoch must be >= 1");
         c->epoch = value; return RASP_OK;
     case RASP_OPT_LDS_WORDS:
-        if (value < 0 || value > 1024 || (value & (value - 1))) return fail(c, RASP_E_INVAL, "lds words must be 0 or a power of two <= 1024");
+        if (value < 0 || value > 1024 || (value & (value - 1)) || (value > 0 && value < 4))
+            return fail(c, RASP_E_INVAL, "lds words must be 0 or a power of two in [4, 1024]");
         c->lds_words = value; return RASP_OK;
     case RASP_OPT_WAVES_PER_CU:
         if (value < 1 || value > 32) return fail(c, RASP_E_INVAL, "waves per CU must be in [1, 32]");
@@ -825,6 +920,8 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
     case RASP_OPT_FIRST_PASS:
         if (value < 0 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "first pass must be >= 0");
         c->first_pass = value; return RASP_OK;
+    case RASP_OPT_PROFILE:
+        c->profile = value ? 1 : 0; return RASP_OK;
     default:
         return fail(c, RASP_E_INVAL, "unknown option %d", option);
     }
@@ -840,8 +937,28 @@ int rasp_get_option(rasp_ctx *c, int option, int64_t *value)
     case RASP_OPT_WAVES_PER_CU: *value = c->waves_per_cu; return RASP_OK;
     case RASP_OPT_GRAPH: *value = c->graph; return RASP_OK;
     case RASP_OPT_FIRST_PASS: *value = c->first_pass; return RASP_OK;
+    case RASP_OPT_PROFILE: *value = c->profile; return RASP_OK;
     default: return fail(c, RASP_E_INVAL, "unknown option %d", option);
     }
+}
+
+int rasp_kernel_times(rasp_ctx *c, double *ms, uint64_t *launches)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &t : c->timed) {
+        float x = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&x, t.a, t.b));
+        if (t.kind >= 0 && t.kind < RASP_KERNEL_COUNT) {
+            if (ms) ms[t.kind] += x;
+            if (launches) launches[t.kind] += 1;
+        }
+        c->ev_pool.push_back(t.a);
+        c->ev_pool.push_back(t.b);
+    }
+    c->timed.clear();
+    return RASP_OK;
 }
 
 int rasp_device_info(rasp_ctx *c, int *cus, int *lds_bytes, int *wave_size)

@@ -29,11 +29,14 @@ RASP_OUT_DEVICE_PTRS = 1
 RASP_OPT_SCHEDULE, RASP_OPT_EPOCH, RASP_OPT_LDS_WORDS = 1, 2, 3
 RASP_OPT_WAVES_PER_CU, RASP_OPT_GRAPH, RASP_OPT_FIRST_PASS = 4, 5, 6
 RASP_SCHED_AUTO, RASP_SCHED_PLAIN, RASP_SCHED_PERSISTENT = 0, 1, 2
+RASP_OPT_PROFILE = 7
+KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other")
 
 EXPORTED = ("rasp_create", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
-            "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info")
+            "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
+            "rasp_kernel_times")
 
 _ERRNAMES = {RASP_E_INVAL: "RASP_E_INVAL", RASP_E_NOMEM: "RASP_E_NOMEM",
              RASP_E_DEVICE: "RASP_E_DEVICE", RASP_E_STATE: "RASP_E_STATE",
@@ -86,6 +89,7 @@ def load_library(path: str = LIB_PATH):
         "rasp_set_option": ([P, i32, i64], i32),
         "rasp_get_option": ([P, i32, ctypes.POINTER(i64)], i32),
         "rasp_device_info": ([P, P, P, P], i32),
+        "rasp_kernel_times": ([P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -273,6 +277,14 @@ def rasp_device_info(ctx) -> dict:
     cu, lds, wv = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     _check(_lib.rasp_device_info(ctx, ctypes.byref(cu), ctypes.byref(lds), ctypes.byref(wv)), ctx)
     return dict(compute_units=cu.value, lds_bytes=lds.value, wave_size=wv.value)
+
+
+def rasp_kernel_times(ctx) -> dict:
+    """{kernel kind: (total ms, launches)} recorded since the last call."""
+    ms = np.zeros(len(KERNEL_NAMES), np.float64)
+    n = np.zeros(len(KERNEL_NAMES), np.uint64)
+    _check(_lib.rasp_kernel_times(ctx, _ptr(ms), _ptr(n)), ctx)
+    return {k: (float(ms[j]), int(n[j])) for j, k in enumerate(KERNEL_NAMES)}
 
 
 # ---- convenience wrapper -------------------------------------------------------------

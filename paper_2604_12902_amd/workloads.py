@@ -152,36 +152,44 @@ def config3(seed: int = 2, num_vms: int = 1 << 22, budget: int = 65536) -> Batch
     memory n log-uniform on [64, 1024] then raised to 2L; data operands on
     [0, n); tape of 32 words on [-100, 100]; output capacity 16.
 
-    Draw order: L (N), n (N), halt slot (N), opcodes (sum L), backward flags
-    (sum L), jump uniforms (sum L), data operands uniforms (sum L), tapes (N x 32).
+    Draw order: L (N), n (N), halt slot (N); then, for each chunk of 2^18
+    machines in order: opcodes, backward flags, jump uniforms, data uniforms
+    (one per instruction of the chunk); finally the tapes (N x 32).
     """
     N = num_vms
     rng = np.random.Generator(np.random.PCG64(seed))
     L = log_uniform_int(rng, 8, 512, N)
     n = np.maximum(log_uniform_int(rng, 64, 1024, N), 2 * L)
     halt_slot = np.floor(rng.random(N) * L).astype(np.int64)
-    tot = int(L.sum())
-    starts = np.cumsum(L) - L
-    vm = np.repeat(np.arange(N, dtype=np.int64), L)
-    k = np.arange(tot, dtype=np.int64) - np.repeat(starts, L)
-    ops = rng.integers(1, 9, size=tot, dtype=np.int64)          # 8 non-HALT opcodes
-    ops[starts + halt_slot] = HALT
-    back = rng.random(tot) < 0.15
-    uj = rng.random(tot)
-    ud = rng.random(tot)
-    Lv = L[vm]
-    tgt_back = np.floor(uj * (k + 1)).astype(np.int64)                   # [0, k]
-    tgt_fwd = k + 1 + np.floor(uj * (Lv - k)).astype(np.int64)           # (k, L]
-    tgt = np.where(back, tgt_back, tgt_fwd)
-    data = np.floor(ud * n[vm]).astype(np.int64)                          # [0, n)
-    is_jump = (ops == JMP) | (ops == JPOS)
-    opd = np.where(is_jump, 2 * tgt, data)
-    opd[ops == HALT] = 0
-    prog = np.empty(2 * tot, dtype=np.int32)
-    prog[0::2] = ops
-    prog[1::2] = opd
+    prog_off = _offsets(2 * L)
+    prog = np.empty(int(prog_off[-1]), dtype=np.int32)
+    chunk = 1 << 18
+    for c0 in range(0, N, chunk):
+        c1 = min(N, c0 + chunk)
+        Lc = L[c0:c1]
+        tot = int(Lc.sum())
+        starts = np.cumsum(Lc) - Lc
+        vm = np.repeat(np.arange(c1 - c0, dtype=np.int64), Lc)
+        k = np.arange(tot, dtype=np.int64) - np.repeat(starts, Lc)
+        ops = rng.integers(1, 9, size=tot, dtype=np.int32)          # 8 non-HALT opcodes
+        ops[starts + halt_slot[c0:c1]] = HALT
+        back = rng.random(tot, dtype=np.float32) < 0.15
+        uj = rng.random(tot)
+        ud = rng.random(tot)
+        Lv = Lc[vm]
+        tgt = np.where(back, np.floor(uj * (k + 1)),                  # [0, k]
+                       k + 1 + np.floor(uj * (Lv - k))).astype(np.int64)   # (k, L]
+        del Lv, uj
+        data = np.floor(ud * n[c0:c1][vm]).astype(np.int64)         # [0, n)
+        del ud, vm, k
+        is_jump = (ops == JMP) | (ops == JPOS)
+        opd = np.where(is_jump, 2 * tgt, data)
+        opd[ops == HALT] = 0
+        base = int(prog_off[c0])
+        prog[base:base + 2 * tot:2] = ops
+        prog[base + 1:base + 2 * tot:2] = opd
     tape = rng.integers(-100, 101, size=(N, 32), dtype=np.int32)
-    return Batch(ISA_CLASSIC, prog, _offsets(2 * L), n.astype(np.uint32),
+    return Batch(ISA_CLASSIC, prog, prog_off, n.astype(np.uint32),
                  tape.reshape(-1), np.arange(N + 1, dtype=np.uint64) * np.uint64(32),
                  np.full(N, 32, np.uint32), np.full(N, 16, np.uint32),
                  budget=budget, name="uneven 4Mx[8,512] n=[64,1024] budget=65536",

@@ -1,0 +1,59 @@
+"""The C ABI library loads and exports every entry point its header declares
+(no compute call: these run without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rasp.h")
+LIB = os.path.join(ROOT, "paper_2604_12902_amd", "librasp.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rasp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("rasp_load_batch", "rasp_run", "rasp_fetch_outputs", "rasp_create",
+                 "rasp_destroy", "rasp_run_multi", "rasp_load_state"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_uses_the_c_names():
+    from paper_2604_12902_amd import rasp
+    for n in declared():
+        assert n in rasp.EXPORTED, n
+        assert callable(getattr(rasp, n)), n
+
+
+def test_last_error_without_context_is_callable():
+    lib = ctypes.CDLL(LIB)
+    lib.rasp_last_error.restype = ctypes.c_char_p
+    lib.rasp_last_error.argtypes = [ctypes.c_void_p]
+    assert isinstance(lib.rasp_last_error(None), bytes)
+
+
+def test_footprint_is_pure_and_checks_descriptors():
+    """rasp_batch_footprint touches no device for a host descriptor."""
+    import numpy as np
+    from paper_2604_12902_amd import rasp, workloads as W
+    b = W.config1(num_vms=10)
+    fp = rasp.rasp_batch_footprint(rasp.make_desc(b))
+    words = int(b.mem_words.sum() + b.tape_cap.sum() + b.out_cap.sum())
+    assert fp >= 4 * words + 25 * 10
+    bad = W.config1(num_vms=10)
+    bad.mem_words = np.full(10, 4, np.uint32)            # program longer than memory
+    try:
+        rasp.rasp_batch_footprint(rasp.make_desc(bad))
+        raise AssertionError("expected RASP_E_INVAL")
+    except rasp.RaspError as e:
+        assert e.code == rasp.RASP_E_INVAL

@@ -1,0 +1,81 @@
+"""Parity at the full population sizes, in the launch configuration the
+benchmark times (default knobs of the persistent schedule).  Every machine's
+scalars are compared where the oracle can afford the whole population;
+otherwise a seeded sample of machines, which the oracle recomputes one by one
+from their own programs, plus properties that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_12902_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    from paper_2604_12902_amd import rasp
+    assert torch.cuda.is_available()
+    return rasp
+
+
+def _run(R, b, arena_extra=1.2):
+    d = R.make_desc(b)
+    ctx = R.Context(int(R.rasp_batch_footprint(d) * arena_extra) + (64 << 20))
+    h = R.rasp_load_batch(ctx.handle, d)
+    ctx.run(h, b.budget)
+    got = ctx.fetch(h, digest=True)
+    info = ctx.info(h, steps_sum=True)
+    ctx.free(h)
+    ctx.close()
+    return got, info
+
+
+def _check_sample(b, got, idx):
+    sub = b.subset(idx)
+    want = oracle.run(sub, b.budget, threads=16)
+    for k in ("status", "steps", "i", "a", "u0", "y0"):
+        assert np.array_equal(got[k][idx], getattr(want, k)), k
+    assert np.array_equal(got["mem_digest"][idx], oracle.digest(want))
+    yo = np.zeros(b.N + 1, np.int64)
+    np.cumsum(b.out_cap.astype(np.int64), out=yo[1:])
+    for j, v in enumerate(idx):
+        assert np.array_equal(got["y"][yo[v]:yo[v + 1]], want.out_of(j)), v
+
+
+def test_plain_scale_every_machine(R):
+    b = W.config2()
+    print("case: plain-scale N=%d" % b.N, flush=True)
+    got, info = _run(R, b)
+    want = oracle.run(b, b.budget, threads=16)
+    for k in ("status", "steps", "i", "a", "u0", "y0"):
+        assert np.array_equal(got[k], getattr(want, k)), k
+    assert np.array_equal(got["y"], want.Y)
+    assert np.array_equal(got["mem_digest"], oracle.digest(want))
+    assert info["steps_sum"] == int(want.steps.sum())
+
+
+def test_uneven_batch_full_size_sampled(R):
+    b = W.config3()
+    print("case: uneven N=%d" % b.N, flush=True)
+    got, info = _run(R, b)
+    rng = np.random.Generator(np.random.PCG64(7))
+    idx = np.sort(rng.choice(b.N, 3000, replace=False))
+    # include the slowest machines the GPU reports, to cover the long tail
+    idx = np.unique(np.concatenate([idx, np.argsort(got["steps"])[-200:]]))
+    _check_sample(b, got, idx)
+    assert (got["steps"] <= b.budget).all() and (got["u0"] <= 32).all()
+    assert (got["y0"] <= 16).all()
+    assert info["steps_sum"] == int(got["steps"].sum())
+
+
+def test_rollouts_full_size_sampled(R):
+    b = W.config4()
+    print("case: rollouts N=%d" % b.N, flush=True)
+    got, info = _run(R, b)
+    rng = np.random.Generator(np.random.PCG64(8))
+    idx = np.sort(rng.choice(b.N, 400, replace=False))
+    _check_sample(b, got, idx)
+    # every rollout program halts well inside its budget
+    assert (got["status"] == 1).all()

@@ -154,3 +154,146 @@ def test_split_budget_and_halted_machines(ctx, rasp):
     for k in ("i", "a", "steps", "u0", "y0"):
         assert np.array_equal(again[k][halted], got[k][halted])
     ctx.free(h)
+
+
+def test_run_multi_equals_separate_runs(ctx, rasp):
+    """One launch over several batches (different shapes and budgets) equals
+    running each batch alone."""
+    configure(ctx, rasp, "firstpass-lds64")
+    batches = [W.config1(seed=21), W.tiny_random(seed=22, num_vms=3000, max_n=40),
+               W.config3(num_vms=3000, seed=23, budget=2000)]
+    budgets = [256, 150, 2000]
+    hs = [ctx.load(b) for b in batches]
+    ctx.run_multi(hs, budgets)
+    for h, b, bud in zip(hs, batches, budgets):
+        compare(ctx.fetch(h, mem=True), oracle.run(b, bud))
+        ctx.free(h)
+
+
+def _random_states(b, seed):
+    """Arbitrary reachable-shaped states: i, a anywhere in int32 (edge values
+    included), u0 <= l, y0 <= s, memory words random with edge values."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    st = oracle.init(b)
+    N = b.N
+    edges = np.array([0, 1, -1, 2, -2, 2 ** 31 - 1, -2 ** 31, 2 ** 31 - 2, -2 ** 31 + 1], np.int64)
+    pick = lambda k: np.where(rng.random(k) < 0.3, edges[rng.integers(0, len(edges), k)],
+                              rng.integers(-2 ** 31, 2 ** 31, k)).astype(np.int32)
+    st.i = np.where(rng.random(N) < 0.5, rng.integers(-4, 40, N), pick(N)).astype(np.int32)
+    st.a = pick(N)
+    st.u0 = np.floor(rng.random(N) * (st.l.astype(np.int64) + 1)).astype(np.uint32)
+    st.y0 = np.floor(rng.random(N) * (st.s.astype(np.int64) + 1)).astype(np.uint32)
+    small = rng.integers(-3, 12, st.mem.size).astype(np.int32)
+    st.mem = np.where(rng.random(st.mem.size) < 0.2, pick(st.mem.size), small).astype(np.int32)
+    st.steps = rng.integers(0, 1000, N).astype(np.uint64)
+    st.Y = rng.integers(-9, 9, st.Y.size).astype(np.int32)
+    return st
+
+
+@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "firstpass-lds16-tiny-epoch"])
+@pytest.mark.parametrize("isa", [0, 1])
+def test_loaded_states_fuzz(ctx, rasp, sched, isa):
+    """rasp_load_state with arbitrary configurations (i near INT32_MAX, odd,
+    negative; a and memory words at the int32 edges; u0 = l; y0 = s), then 1
+    and 37 transitions, against the oracle advanced from the same state."""
+    configure(ctx, rasp, sched)
+    b = W.tiny_random(seed=40 + isa, num_vms=4000, isa=isa, max_m=6, max_n=30, max_ell=4,
+                      max_s=3, opcode_hi=10)
+    st = _random_states(b, seed=41 + isa)
+    state = dict(i=st.i, a=st.a, u0=st.u0, y0=st.y0, steps=st.steps, y=st.Y, mem=st.mem)
+    h = ctx.load_state(b, state)
+    got0 = ctx.fetch(h, mem=True)
+    want = st.copy()
+    oracle.advance(want, 0)
+    compare(got0, want)
+    for budget in (1, 37):
+        ctx.run(h, budget)
+        oracle.advance(want, budget)
+        compare(ctx.fetch(h, mem=True), want)
+    ctx.free(h)
+
+
+def test_order_and_halves(ctx, rasp):
+    """A permuted batch gives permuted results; a batch equals its two halves
+    run separately (machines are independent)."""
+    configure(ctx, rasp, "firstpass-lds64")
+    b = W.config3(num_vms=4000, seed=31, budget=3000)
+    full = run_gpu(ctx, b, 3000)
+    perm = np.random.Generator(np.random.PCG64(3)).permutation(b.N)
+    pg = run_gpu(ctx, b.subset(perm), 3000, mem=False)
+    for k in ("status", "steps", "i", "a", "u0", "y0"):
+        assert np.array_equal(pg[k], full[k][perm])
+    lo = run_gpu(ctx, b.subset(np.arange(2000)), 3000)
+    hi = run_gpu(ctx, b.subset(np.arange(2000, 4000)), 3000)
+    for k in ("status", "steps", "i", "a", "u0", "y0", "y", "mem"):
+        assert np.array_equal(np.concatenate([lo[k], hi[k]]), full[k]), k
+
+
+def test_device_descriptor_and_digest(ctx, rasp):
+    """A descriptor of device-resident arrays (ragged shapes) loads the same
+    c0 as a host one; memory digests equal the oracle's FNV-1a hashes."""
+    configure(ctx, rasp, "firstpass-lds64")
+    b = W.config3(num_vms=5000, seed=33, budget=1000)
+    d = rasp.make_desc(b, ctx.device)
+    h = rasp.rasp_load_batch(ctx.handle, d)
+    ctx.run(h, 1000)
+    got = ctx.fetch(h, mem=True, digest=True)
+    ctx.free(h)
+    want = oracle.run(b, 1000)
+    compare(got, want)
+    assert np.array_equal(got["mem_digest"], oracle.digest(want))
+
+
+def test_error_paths(ctx, rasp):
+    R = rasp
+    b = W.config1(num_vms=8)
+    # program longer than memory -> INVAL, nothing allocated
+    bad = W.config1(num_vms=8)
+    bad.mem_words = bad.mem_words.copy()
+    bad.mem_words[3] = 10
+    with pytest.raises(R.RaspError) as e:
+        ctx.load(bad)
+    assert e.value.code == R.RASP_E_INVAL
+    # same check on the device path
+    with pytest.raises(R.RaspError) as e:
+        R.rasp_load_batch(ctx.handle, R.make_desc(bad, ctx.device))
+    assert e.value.code == R.RASP_E_INVAL
+    # decreasing offsets
+    bad2 = W.config1(num_vms=8)
+    bad2.prog_off = bad2.prog_off.copy()
+    bad2.prog_off[4] = bad2.prog_off[5] + 1
+    with pytest.raises(R.RaspError) as e:
+        ctx.load(bad2)
+    assert e.value.code == R.RASP_E_INVAL
+    # unknown handle, double free
+    h = ctx.load(b)
+    ctx.free(h)
+    with pytest.raises(R.RaspError) as e:
+        ctx.free(h)
+    assert e.value.code == R.RASP_E_STATE
+    with pytest.raises(R.RaspError) as e:
+        ctx.run(h, 5)
+    assert e.value.code == R.RASP_E_STATE
+    # state with u0 > l
+    st = oracle.init(b)
+    st.u0 = st.u0.copy()
+    st.u0[0] = int(st.l[0]) + 1
+    with pytest.raises(R.RaspError) as e:
+        ctx.load_state(b, dict(i=st.i, a=st.a, u0=st.u0, y0=st.y0, mem=st.mem))
+    assert e.value.code == R.RASP_E_INVAL
+    # arena too small
+    small = R.Context(2 << 20)
+    with pytest.raises(R.RaspError) as e:
+        small.load(W.config2(num_vms=20000))
+    assert e.value.code == R.RASP_E_NOMEM
+    small.close()
+    # the context still works after all of the above
+    compare(run_gpu(ctx, b, 256), oracle.run(b, 256))
+
+
+def test_budget_zero_reports_fixed_points_of_c0(ctx, rasp):
+    configure(ctx, rasp, "plain")
+    b = W.config1()
+    got = run_gpu(ctx, b, 0)
+    compare(got, oracle.run(b, 0))
+    assert got["status"].any() and not got["status"].all()

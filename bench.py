@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--lds-words", type=int, default=None)
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
+    ap.add_argument("--lazy", action="store_true",
+                    help="load with RASP_DESC_LAZY (c0 built inside the run)")
     ap.add_argument("--json-extra", default="", help="path to write the full report")
     return ap.parse_args()
 
@@ -123,7 +125,8 @@ def main():
         cores, cpu_s, total_steps, bstep), flush=True)
 
     dev = torch.device("cuda", 0)
-    desc = R.make_desc(batch, dev)                     # inputs resident in HBM
+    # inputs resident in HBM (with --lazy, c0 is built inside the run)
+    desc = R.make_desc(batch, dev, lazy=args.lazy)
     N = batch.N
     outs = dict(status=torch.empty(N, dtype=torch.uint8, device=dev),
                 steps=torch.empty(N, dtype=torch.int64, device=dev),
@@ -213,10 +216,17 @@ def main():
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
     dom_ms = kt[dom][0] / kt[dom][1]
     fp_pass = int(ctx.get(R.RASP_OPT_FIRST_PASS))
+    fused = kt["pack"][1] == 0 and kt["plain"][1] == 0
+    if fused:
+        fp_pass = 0
     steps_plain_pass = int(np.minimum(ref.steps.astype(np.int64), fp_pass).sum())
     if dom == "pack":
         algo = pack_bytes(batch)
         unit_note = "c0 bytes: programs + inputs read, n+l+s words + 25 B scalars written per machine"
+    elif dom == "persistent" and fused:
+        algo = pack_bytes(batch) + bstep * total_steps + 25.0 * N
+        unit_note = ("c0 built in the launch (programs + inputs read, n+l+s words + 25 B scalars "
+                     "written per machine) + %.2f B per retired step + 25 B final state per machine" % bstep)
     elif dom == "persistent":
         algo = bstep * (total_steps - steps_plain_pass) + 50.0 * int((ref.steps > fp_pass).sum())
         unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
@@ -248,6 +258,7 @@ def main():
         "config": {"workload": batch.name, "num_vms": N, "budget": budget,
                    "retired_steps_per_batch": total_steps, "schedule": "persistent",
                    "first_pass": fp_pass, "lds_words": int(ctx.get(R.RASP_OPT_LDS_WORDS)),
+                   "c0_in_run": bool(fused),
                    "epoch": int(ctx.get(R.RASP_OPT_EPOCH)),
                    "waves_per_cu": int(ctx.get(R.RASP_OPT_WAVES_PER_CU))},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],

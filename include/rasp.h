@@ -75,7 +75,14 @@ enum {
 enum { RASP_RUNNING = 0, RASP_HALTED = 1 };
 
 /* rasp_batch_desc.flags */
-enum { RASP_DESC_DEVICE_PTRS = 1u };  /* every array of the descriptor is device memory */
+enum {
+    RASP_DESC_DEVICE_PTRS = 1u,  /* every array of the descriptor is device memory */
+    RASP_DESC_LAZY = 2u          /* with DEVICE_PTRS: build c0 inside the first rasp_run
+                                    (each machine's c0 is written straight into its LDS
+                                    slot by the step kernel and then to the arena); the
+                                    descriptor arrays are read until that run, or the
+                                    first call that needs the state, has finished */
+};
 
 /* rasp_outputs.flags */
 enum { RASP_OUT_DEVICE_PTRS = 1u };   /* every destination is device memory */
@@ -114,7 +121,8 @@ const char *rasp_last_error(const rasp_ctx *ctx);
  * With RASP_DESC_DEVICE_PTRS every pointer is device memory on the context's
  * device; otherwise host memory.  The arrays are only read, and only until the
  * call that takes the descriptor returns (host) or until the work it queues
- * has finished on the context stream (device).
+ * has finished on the context stream (device; with RASP_DESC_LAZY until the
+ * batch's first run or fetch has finished).
  */
 typedef struct {
     uint32_t abi_version;            /* RASP_ABI_VERSION */
@@ -225,6 +233,14 @@ int rasp_fetch_outputs(rasp_ctx *ctx, rasp_batch b, const rasp_outputs *out);
  */
 int rasp_batch_info(rasp_ctx *ctx, rasp_batch b, uint64_t *num_vms, uint64_t *mem_words,
                     uint64_t *out_words, uint64_t *steps_sum);
+
+/*
+ * rasp_running_counts: for k batches (k <= 64), counts[t] = number of machines
+ * of bs[t] not at a fixed point, from one device launch and one wait.  Used by
+ * a serving loop to retire requests whose machines have all halted.
+ * Errors: INVAL, STATE, DEVICE.
+ */
+int rasp_running_counts(rasp_ctx *ctx, const rasp_batch *bs, uint32_t k, uint64_t *counts);
 
 /* rasp_free_batch: release a batch's arena space after its queued work. */
 int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);

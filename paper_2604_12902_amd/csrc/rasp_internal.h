@@ -32,7 +32,11 @@ struct DevBatch {
     int32_t *Y;
     uint64_t N;
     uint32_t isa;
-    uint32_t pad;
+    uint32_t fresh;                    // 1: state is c0, built from the packed inputs below
+    const int32_t *prog;               // packed programs / inputs of a fresh batch
+    const uint64_t *prog_off;
+    const int32_t *tape;
+    const uint64_t *tape_off;
 };
 
 // Table of batches advanced together by one launch.  Machine g of the launch
@@ -84,12 +88,14 @@ hipError_t launch_pack(DevBatch b, const int32_t *prog, const uint64_t *prog_off
 hipError_t launch_check_state(DevBatch b, uint32_t *err, hipStream_t st);
 hipError_t launch_probe(DevBatch b, hipStream_t st);
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap,
-                        uint32_t isa, uint32_t *surv, QueueState *q, hipStream_t st);
+                        uint32_t isa, bool pow2, uint32_t *surv, QueueState *q, hipStream_t st);
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
-                             uint32_t already, uint32_t isa, uint32_t epoch, uint32_t lds_words,
+                             uint32_t already, uint32_t isa, bool pow2, uint32_t epoch, uint32_t lds_words,
                              uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
                              QueueState *q, hipStream_t st);
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
+hipError_t launch_running(const BatchTable *tab, uint64_t total, unsigned long long *counts,
+                          hipStream_t st);
 hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st);
 hipError_t launch_steps_sum(DevBatch b, unsigned long long *out, hipStream_t st);
 hipError_t launch_gather_words(const int32_t *src, const uint64_t *off, const uint32_t *len,

@@ -130,81 +130,91 @@ struct Regs {
 // Software-pipelined: the words of the next instruction are loaded together
 // with the data word of the current one (after the current store, so that a
 // program that rewrites its next instruction sees the new word), leaving one
-// memory round trip per transition.  The common case -- operand word already
-// in [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code;
+// memory round trip per transition; the loop has a single exit.
+// POW2 (n a power of two): v mod n = v & (n-1) for every int32 v, and
+// (i + k) mod n = (p + k) mod n across the int32 wrap, so positions need no
+// division and no special case.  Otherwise the common case -- operand word in
+// [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code and
 // everything else takes one branch that lanes skip when none needs it.
-template <int ISA, class Mem>
+template <int ISA, bool POW2, class Mem>
 __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
                                                 const int32_t *__restrict__ T,
                                                 int32_t *__restrict__ Y,
                                                 uint32_t limit, bool &halted, bool &wrote)
 {
-    uint32_t t = 0;
-    int32_t o = mem.ld(r.p);
-    int32_t j = mem.ld(operand_pos(r.i, r.p, r.n));
+    const uint32_t n = r.n, nm = r.n - 1u, ell = r.ell, s = r.s;
+    uint32_t p = r.p, u0 = r.u0, y0 = r.y0;
+    int32_t i = r.i, a = r.a;
+    int32_t o = mem.ld(p);
+    int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n));
+    uint32_t left = limit;
+    bool wr = false, fixed;
     for (;;) {
         const uint32_t op = static_cast<uint32_t>(o);
-        bool is_ld, is_add, is_sub, is_mul, is_sto, is_rd, is_pr, taken, valid;
-        is_ld = op == 1u;
-        is_add = op == 2u;
-        is_sto = op == 4u;
-        is_rd = op == 6u;
-        is_pr = op == 7u;
-        if (ISA == 1) {                  // classic: SUB, JPOS (a > 0), JMP
-            is_sub = op == 3u;
-            is_mul = false;
-            taken = (op == 8u) | ((op == 5u) & (r.a > 0));
+        const bool is_rd = op == 6u;
+        bool taken, valid;
+        if (ISA == 1) {                  // classic: JPOS (a > 0), JMP
+            taken = (op == 8u) | ((op == 5u) & (a > 0));
             valid = (op - 1u) < 8u;
-        } else {                         // word: MUL, BNZ (a != 0)
-            is_sub = false;
-            is_mul = op == 3u;
-            taken = (op == 5u) & (r.a != 0);
+        } else {                         // word: BNZ (a != 0)
+            taken = (op == 5u) & (a != 0);
             valid = (op - 1u) < 7u;
         }
-        const bool rd_ok = is_rd & (r.u0 < r.ell);
-        const bool fixed = !valid | (is_rd & !rd_ok) | (taken & (j == r.i));
-        if (fixed) { halted = true; break; }
-        if (t == limit) { halted = false; break; }
+        const bool rd_ok = is_rd & (u0 < ell);
+        fixed = !valid | (is_rd & !rd_ok) | (taken & (j == i));
+        if (fixed | (left == 0u)) break;
 
         // positions: data word jj = j mod n, next instruction np, its operand nq
-        uint32_t jj = static_cast<uint32_t>(j);
-        uint32_t seq = r.p + 2u;
-        seq = seq >= r.n ? seq - r.n : seq;
-        const bool rare = (static_cast<uint32_t>(j) >= r.n) | (r.i >= INT32_MAX - 3) | (r.n < 2u);
-        if (rare) {
-            jj = cmod(j, r.n);
-            seq = advance_pos(r.i, r.p, r.n);
+        uint32_t jj, seq, np, nq;
+        const int32_t ni = taken ? j : static_cast<int32_t>(static_cast<uint32_t>(i) + 2u);
+        if (POW2) {
+            jj = static_cast<uint32_t>(j) & nm;
+            seq = (p + 2u) & nm;
+            np = taken ? jj : seq;
+            nq = (np + 1u) & nm;
+        } else {
+            jj = static_cast<uint32_t>(j);
+            seq = p + 2u;
+            seq = seq >= n ? seq - n : seq;
+            const bool rare = (static_cast<uint32_t>(j) >= n) | (i >= INT32_MAX - 3) | (n < 2u);
+            if (rare) {
+                jj = cmod(j, n);
+                seq = advance_pos(i, p, n);
+            }
+            np = taken ? jj : seq;
+            nq = np + 1u;
+            nq = nq == n ? 0u : nq;
+            if (rare) nq = operand_pos(ni, np, n);
         }
-        const int32_t ni = taken ? j : static_cast<int32_t>(static_cast<uint32_t>(r.i) + 2u);
-        const uint32_t np = taken ? jj : seq;
-        uint32_t nq = np + 1u;
-        nq = nq == r.n ? 0u : nq;
-        if (rare) nq = operand_pos(ni, np, r.n);
 
-        const bool st_en = is_sto | rd_ok;
-        int32_t w = r.a;
-        if (rd_ok) w = T[r.u0];
+        const bool st_en = (op == 4u) | rd_ok;
+        int32_t w = a;
+        if (rd_ok) w = T[u0];
         mem.st(jj, w, st_en);
-        wrote |= st_en;
-        r.u0 += rd_ok ? 1u : 0u;
-        const int32_t d = mem.ld_data(jj, is_add | is_sub | is_mul | is_pr);
+        wr |= st_en;
+        u0 += rd_ok ? 1u : 0u;
+        const bool need = (op == 2u) | (op == 3u) | (op == 7u);
+        const int32_t d = mem.ld_data(jj, need);
         const int32_t jcur = j;
         o = mem.ld(np);
         j = mem.ld(nq);
 
-        const uint32_t ua = static_cast<uint32_t>(r.a), ud = static_cast<uint32_t>(d);
-        uint32_t na = ua;
-        if (ISA == 1) na = is_sub ? ua - ud : na;
-        else na = is_mul ? ua * ud : na;
-        na = is_add ? ua + ud : na;
-        na = is_ld ? static_cast<uint32_t>(jcur) : na;
-        r.a = static_cast<int32_t>(na);
-        if (is_pr & (r.y0 < r.s)) { Y[r.y0] = d; r.y0 += 1u; }
-        r.i = ni;
-        r.p = np;
-        ++t;
+        const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);
+        uint32_t na = op == 3u ? (ISA == 1 ? ua - ud : ua * ud) : ua;
+        na = op == 2u ? ua + ud : na;
+        na = op == 1u ? static_cast<uint32_t>(jcur) : na;
+        a = static_cast<int32_t>(na);
+        const bool app = (op == 7u) & (y0 < s);
+        if (app) Y[y0] = d;
+        y0 += app ? 1u : 0u;
+        i = ni;
+        p = np;
+        --left;
     }
-    return t;
+    halted = fixed;
+    wrote |= wr;
+    r.i = i; r.a = a; r.p = p; r.u0 = u0; r.y0 = y0;
+    return limit - left;
 }
 
 __device__ __forceinline__ int batch_of(const BatchTable *tab, uint64_t g)
@@ -306,7 +316,7 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     r.p = cmod(r.i, r.n);
     GlobalMem g{b.M + b.mem_off[v]};
     bool halted, wrote = false;
-    run_machine<ISA>(g, r, b.T + b.t_off[v], b.Y + b.y_off[v], 0u, halted, wrote);
+    run_machine<ISA, false>(g, r, b.T + b.t_off[v], b.Y + b.y_off[v], 0u, halted, wrote);
     b.status[v] = halted ? 1 : 0;
 }
 
@@ -325,7 +335,7 @@ hipError_t launch_probe(DevBatch b, hipStream_t st)
 // atomic) to the survivor list for the persistent kernel.
 // ---------------------------------------------------------------------------
 
-template <int ISA>
+template <int ISA, bool POW2>
 __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ tab, uint64_t total,
                                                uint32_t cap, uint32_t *__restrict__ surv,
                                                QueueState *__restrict__ q)
@@ -345,8 +355,8 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             const uint32_t limit = cap < budget ? cap : budget;
             GlobalMem m{b.M + b.mem_off[v]};
             bool halted, wrote = false;
-            const uint32_t t = run_machine<ISA>(m, r, b.T + b.t_off[v], b.Y + b.y_off[v], limit,
-                                                halted, wrote);
+            const uint32_t t = run_machine<ISA, POW2>(m, r, b.T + b.t_off[v], b.Y + b.y_off[v], limit,
+                                                      halted, wrote);
             if (t) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
                 b.steps[v] += t;
@@ -373,11 +383,16 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
 }
 
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uint32_t isa,
-                        uint32_t *surv, QueueState *q, hipStream_t st)
+                        bool pow2, uint32_t *surv, QueueState *q, hipStream_t st)
 {
     const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
-    if (isa == 1) k_plain<1><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
-    else k_plain<0><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+    if (isa == 1) {
+        if (pow2) k_plain<1, true><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+        else k_plain<1, false><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+    } else {
+        if (pow2) k_plain<0, true><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+        else k_plain<0, false><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+    }
     return hipGetLastError();
 }
 
@@ -395,7 +410,7 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uin
 // is null); machines have already applied `already` transitions this run.
 // ---------------------------------------------------------------------------
 
-template <int ISA, int MODE>
+template <int ISA, int MODE, bool POW2>
 __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict__ tab,
                                                     uint64_t total,
                                                     const uint32_t *__restrict__ work,
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
     const uint32_t slot = wave_base + lane * SP;
     if (work != nullptr) total = q->survivors;             // written by the plain pass
 
-    bool has = false, exhausted = false, wrote = false;
+    bool has = false, exhausted = false, wrote = false, fresh = false;
     Regs r{};
     int32_t *M = nullptr;
     const int32_t *T = nullptr;
@@ -421,7 +436,7 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
     for (;;) {
         // ---- refill idle lanes from the queue ----
         const uint64_t idle = __ballot(!has);
-        uint64_t fresh_mask = 0;
+        bool claimed = false;
         if (idle != 0 && !exhausted) {
             const int leader = __ffsll(static_cast<unsigned long long>(idle)) - 1;
             const uint32_t cnt = __popcll(idle);
@@ -431,7 +446,6 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             base = __shfl(base, leader);
             if (base + cnt >= total) exhausted = true;
-            bool fresh = false;
             if (!has) {
                 const uint64_t item = base + __popcll(idle & ((1ull << lane) - 1ull));
                 if (item < total) {
@@ -440,9 +454,14 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                     bp = &tab->b[k];
                     v = g - tab->start[k];
                     const uint32_t budget = tab->budget[k];
-                    if (bp->status[v] == 0 && budget > already) {
+                    fresh = bp->fresh != 0;
+                    if ((fresh || bp->status[v] == 0) && budget > already) {
                         r.n = bp->n[v]; r.ell = bp->ell[v]; r.s = bp->s[v];
-                        r.i = bp->i[v]; r.a = bp->a[v]; r.u0 = bp->u0[v]; r.y0 = bp->y0[v];
+                        if (fresh) {
+                            r.i = 0; r.a = 0; r.u0 = 0; r.y0 = 0;
+                        } else {
+                            r.i = bp->i[v]; r.a = bp->a[v]; r.u0 = bp->u0[v]; r.y0 = bp->y0[v];
+                        }
                         r.p = cmod(r.i, r.n);
                         M = bp->M + bp->mem_off[v];
                         T = bp->T + bp->t_off[v];
@@ -451,31 +470,65 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                         limit = budget - already;
                         wrote = false;
                         has = true;
-                        fresh = true;
+                        claimed = true;
                     }
                 }
             }
-            fresh_mask = __ballot(fresh);
         }
         if (__ballot(has) == 0) {
             if (exhausted) break;
             continue;
         }
-        // ---- stage the fresh machines' low memory words into LDS ----
-        if (MODE != 0) {
-            uint64_t m = fresh_mask;
-            while (m) {
-                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
-                m &= m - 1;
-                const int32_t *src = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L));
-                const uint32_t nL = bcast(r.n, L);
-                const uint32_t cnt = nL < P ? nL : P;
-                const uint32_t dst = wave_base + L * SP;
-                for (uint32_t k = 4 * lane; k < cnt; k += 4 * kWave)
-                    *reinterpret_cast<int4 *>(&rasp_lds[dst + k]) = *reinterpret_cast<const int4 *>(src + k);
+        // ---- stage the claimed machine's low memory words into the lane's slot ----
+        if (MODE != 0 && claimed) {
+            const uint32_t cnt = r.n < P ? r.n : P;
+            if (fresh) {
+                // c0 (Sec. 2.1): program words, zeros; tape x 0^(l-|x|); output 0^s
+                const uint64_t p0 = bp->prog_off[v];
+                const uint32_t plen = static_cast<uint32_t>(bp->prog_off[v + 1] - p0);
+                const int32_t *src = bp->prog + p0;
+                const bool al = (p0 & 3u) == 0;
+                // groups of 8 x 16 bytes: every load of a group is issued before its stores
+                for (uint32_t k0 = 0; k0 < cnt; k0 += 32) {
+                    int4 w[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const uint32_t k = k0 + 4u * u;
+                        if (al && k + 4 <= plen) {
+                            w[u] = *reinterpret_cast<const int4 *>(src + k);
+                        } else {
+                            w[u].x = k < plen ? src[k] : 0;
+                            w[u].y = k + 1 < plen ? src[k + 1] : 0;
+                            w[u].z = k + 2 < plen ? src[k + 2] : 0;
+                            w[u].w = k + 3 < plen ? src[k + 3] : 0;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + 4u * u < cnt) *reinterpret_cast<int4 *>(&rasp_lds[slot + k0 + 4u * u]) = w[u];
+                }
+                const uint64_t t0 = bp->tape_off[v];
+                const uint32_t tlen = static_cast<uint32_t>(bp->tape_off[v + 1] - t0);
+                int32_t *Tw = const_cast<int32_t *>(T);
+                for (uint32_t e0 = 0; e0 < r.ell; e0 += 8) {
+                    int32_t x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x[u] = e0 + u < tlen ? bp->tape[t0 + e0 + u] : 0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) if (e0 + u < r.ell) Tw[e0 + u] = x[u];
+                }
+                for (uint32_t e = 0; e < r.s; ++e) Y[e] = 0;
+            } else {
+                for (uint32_t k0 = 0; k0 < cnt; k0 += 32) {
+                    int4 w[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + 4u * u < cnt) w[u] = *reinterpret_cast<const int4 *>(M + k0 + 4u * u);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + 4u * u < cnt) *reinterpret_cast<int4 *>(&rasp_lds[slot + k0 + 4u * u]) = w[u];
+                }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
         // ---- run ----
         bool finish = false;
@@ -486,82 +539,83 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             uint32_t t;
             if (MODE == 1) {
                 LdsMem mm{slot, slot + P};
-                t = run_machine<ISA>(mm, r, T, Y, lim, halted, wrote);
+                t = run_machine<ISA, POW2>(mm, r, T, Y, lim, halted, wrote);
             } else if (MODE == 2) {
                 SplitMem mm{slot, P, M};
-                t = run_machine<ISA>(mm, r, T, Y, lim, halted, wrote);
+                t = run_machine<ISA, POW2>(mm, r, T, Y, lim, halted, wrote);
             } else {
                 GlobalMem mm{M};
-                t = run_machine<ISA>(mm, r, T, Y, lim, halted, wrote);
+                t = run_machine<ISA, POW2>(mm, r, T, Y, lim, halted, wrote);
             }
             done += t;
             if (halted || done == limit) {
-                if (done) {
+                if (done || fresh) {
                     bp->i[v] = r.i; bp->a[v] = r.a; bp->u0[v] = r.u0; bp->y0[v] = r.y0;
-                    bp->steps[v] += done;
+                    bp->steps[v] = fresh ? done : bp->steps[v] + done;
                 }
-                if (halted) bp->status[v] = 1;
+                if (halted || fresh) bp->status[v] = halted ? 1 : 0;
                 finish = true;
             }
         }
-        // ---- write back staged words of finished machines that stored ----
-        if (MODE != 0) {
-            uint64_t m = __ballot(finish && wrote);
-            if (m) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
+        // ---- write back the slot of a finished machine that stored (or is new) ----
+        if (MODE != 0 && finish && (wrote || fresh)) {
+            const uint32_t cnt = r.n < P ? r.n : P;
+            for (uint32_t k0 = 0; k0 < cnt; k0 += 32) {
+                int4 w[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + 4u * u < cnt) w[u] = *reinterpret_cast<const int4 *>(&rasp_lds[slot + k0 + 4u * u]);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k0 + 4u * u < cnt) *reinterpret_cast<int4 *>(M + k0 + 4u * u) = w[u];
             }
-            while (m) {
-                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
-                m &= m - 1;
-                int32_t *dstp = reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L));
-                const uint32_t nL = bcast(r.n, L);
-                const uint32_t cnt = nL < P ? nL : P;
-                const uint32_t src = wave_base + L * SP;
-                for (uint32_t k = 4 * lane; k < cnt; k += 4 * kWave)
-                    *reinterpret_cast<int4 *>(dstp + k) = *reinterpret_cast<const int4 *>(&rasp_lds[src + k]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
         if (finish) has = false;
     }
 }
 
-template <int MODE>
-static void set_lds_attr()
+template <int ISA, int MODE, bool POW2>
+static hipError_t launch_k3(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const BatchTable *tab,
+                            uint64_t total, const uint32_t *work, uint32_t already, uint32_t epoch,
+                            uint32_t P, QueueState *q)
 {
-    static bool done = false;
-    if (done) return;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<1, MODE>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<0, MODE>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipGetLastError();
-    done = true;
+    static bool attr = false;
+    if (MODE != 0 && !attr) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<ISA, MODE, POW2>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipGetLastError();
+        attr = true;
+    }
+    k_persistent<ISA, MODE, POW2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, P, q);
+    return hipGetLastError();
+}
+
+template <int ISA, int MODE>
+static hipError_t launch_k3_p(bool pow2, dim3 grid, dim3 block, size_t shmem, hipStream_t st,
+                              const BatchTable *tab, uint64_t total, const uint32_t *work,
+                              uint32_t already, uint32_t epoch, uint32_t P, QueueState *q)
+{
+    return pow2 ? launch_k3<ISA, MODE, true>(grid, block, shmem, st, tab, total, work, already, epoch, P, q)
+                : launch_k3<ISA, MODE, false>(grid, block, shmem, st, tab, total, work, already, epoch, P, q);
 }
 
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
-                             uint32_t already, uint32_t isa, uint32_t epoch, uint32_t lds_words,
+                             uint32_t already, uint32_t isa, bool pow2, uint32_t epoch, uint32_t lds_words,
                              uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
                              QueueState *q, hipStream_t st)
 {
     const dim3 grid(blocks), block(waves_per_block * kWave);
-    const size_t shmem = static_cast<size_t>(waves_per_block) * kWave * (lds_words + 4) * sizeof(int32_t);
     const int mode = lds_words == 0 ? 0 : (max_n <= lds_words ? 1 : 2);
-    if (mode == 1) {
-        set_lds_attr<1>();
-        if (isa == 1) k_persistent<1, 1><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
-        else k_persistent<0, 1><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
-    } else if (mode == 2) {
-        set_lds_attr<2>();
-        if (isa == 1) k_persistent<1, 2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
-        else k_persistent<0, 2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, lds_words, q);
-    } else {
-        if (isa == 1) k_persistent<1, 0><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
-        else k_persistent<0, 0><<<grid, block, 0, st>>>(tab, total, work, already, epoch, 0u, q);
+    const size_t shmem = mode == 0 ? 0 : static_cast<size_t>(waves_per_block) * kWave * (lds_words + 4) * sizeof(int32_t);
+    const uint32_t P = mode == 0 ? 0u : lds_words;
+    if (isa == 1) {
+        if (mode == 1) return launch_k3_p<1, 1>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+        if (mode == 2) return launch_k3_p<1, 2>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+        return launch_k3_p<1, 0>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
     }
-    return hipGetLastError();
+    if (mode == 1) return launch_k3_p<0, 1>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+    if (mode == 2) return launch_k3_p<0, 2>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+    return launch_k3_p<0, 0>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
 }
 
 __global__ void k_zero_queue(QueueState *q)
@@ -609,6 +663,37 @@ __global__ __launch_bounds__(256) void k_digest(DevBatch b, uint64_t *__restrict
 hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st)
 {
     k_digest<<<static_cast<unsigned>((b.N + 255) / 256), 256, 0, st>>>(b, out);
+    return hipGetLastError();
+}
+
+// per-batch count of machines not at a fixed point
+__global__ __launch_bounds__(256) void k_running(const BatchTable *__restrict__ tab, uint64_t total,
+                                                 unsigned long long *__restrict__ counts)
+{
+    const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int k = 0;
+    bool run = false;
+    if (g < total) {
+        k = batch_of(tab, g);
+        run = tab->b[k].status[g - tab->start[k]] == 0;
+    }
+    // lanes of a wave may span two batches: aggregate per batch of the leader
+    uint64_t rem = __ballot(g < total);
+    while (rem) {
+        const int leader = __ffsll(static_cast<unsigned long long>(rem)) - 1;
+        const int kl = __shfl(k, leader);
+        const uint64_t mine = __ballot(g < total && k == kl);
+        const uint64_t cnt = __popcll(__ballot(g < total && k == kl && run));
+        if ((threadIdx.x & (kWave - 1)) == static_cast<uint32_t>(leader) && cnt)
+            atomicAdd(&counts[kl], static_cast<unsigned long long>(cnt));
+        rem &= ~mine;
+    }
+}
+
+hipError_t launch_running(const BatchTable *tab, uint64_t total, unsigned long long *counts,
+                          hipStream_t st)
+{
+    k_running<<<static_cast<unsigned>((total + 255) / 256), 256, 0, st>>>(tab, total, counts);
     return hipGetLastError();
 }
 
@@ -666,23 +751,30 @@ __global__ __launch_bounds__(256) void k_shapes(const uint64_t *__restrict__ pro
     (void)max_n;
 }
 
-// maximum of a u32 array: a fixed grid of 256 blocks, grid-stride, one
-// atomic per block
+// maximum memory size and "some size is not a power of two": a fixed grid
+// of 256 blocks, grid-stride, one atomic per block; out[0] = max, out[1] != 0
+// iff some n is not a power of two
 __global__ __launch_bounds__(256) void k_max_u32(const uint32_t *__restrict__ in, uint64_t N,
                                                  uint32_t *__restrict__ out)
 {
-    __shared__ uint32_t wmax[256 / kWave];
-    uint32_t mx = 0;
+    __shared__ uint32_t wmax[256 / kWave], wor[256 / kWave];
+    uint32_t mx = 0, np2 = 0;
     for (uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < N;
-         v += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-        mx = max(mx, in[v]);
-    for (int off = kWave / 2; off > 0; off >>= 1)
+         v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t n = in[v];
+        mx = max(mx, n);
+        np2 |= (n & (n - 1u)) ? 1u : 0u;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
         mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), off)));
-    if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = mx;
+        np2 |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(np2), off));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) { wmax[threadIdx.x / kWave] = mx; wor[threadIdx.x / kWave] = np2; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < static_cast<int>(blockDim.x / kWave); ++w) mx = max(mx, wmax[w]);
+        for (int w = 1; w < static_cast<int>(blockDim.x / kWave); ++w) { mx = max(mx, wmax[w]); np2 |= wor[w]; }
         atomicMax(out, mx);
+        if (np2) atomicOr(out + 1, 1u);
     }
 }
 

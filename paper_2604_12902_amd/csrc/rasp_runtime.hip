@@ -82,6 +82,7 @@ struct Batch {
     uint64_t N = 0;
     uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
     uint32_t max_n = 0;
+    bool all_pow2 = false;               // every n a power of two
     bool uniform_dense = false;          // every n a multiple of 4: padded == dense
     bool status_stale = true;            // status not yet computed since the load
 };
@@ -148,7 +149,7 @@ struct rasp_ctx {
     // device properties
     int cus = 0, lds_bytes = 0, wave = 64;
     // options
-    int64_t schedule = RASP_SCHED_AUTO, epoch = 64, lds_words = 0, waves_per_cu = 8, graph = 0;
+    int64_t schedule = RASP_SCHED_AUTO, epoch = 256, lds_words = -1, waves_per_cu = 16, graph = 0;
     int64_t first_pass = 64;
     // scratch: queue counters, batch tables (device ring + pinned host ring)
     Alloc scratch;
@@ -162,6 +163,7 @@ struct rasp_ctx {
     uint64_t work_cap = 0;
     uint32_t *err_host = nullptr;        // pinned: error word and totals
     uint64_t *tot_host = nullptr;
+    uint64_t *count_host = nullptr;      // pinned: running counts
     // kernel timing (RASP_OPT_PROFILE)
     int64_t profile = 0;
     struct Timed { int kind; hipEvent_t a, b; };
@@ -228,6 +230,20 @@ Batch *find(rasp_ctx *c, rasp_batch b)
     return it == c->batches.end() ? nullptr : it->second.get();
 }
 
+template <class F> hipError_t timed_launch(rasp_ctx *c, int kind, F fn);
+
+// Build c0 of a lazily loaded batch (RASP_DESC_LAZY) in the arena.
+int materialize(rasp_ctx *c, Batch *b)
+{
+    if (!b->dev.fresh) return RASP_OK;
+    DevBatch d = b->dev;
+    HIPCHK(c, timed_launch(c, RASP_KERNEL_PACK, [&] {
+        return launch_pack(d, d.prog, d.prog_off, d.tape, d.tape_off, c->stream); }));
+    b->dev.fresh = 0;
+    b->status_stale = true;
+    return RASP_OK;
+}
+
 hipEvent_t pooled_event(rasp_ctx *c)
 {
     if (!c->ev_pool.empty()) {
@@ -263,6 +279,7 @@ struct HostShapes {
     uint64_t prog_words = 0, tape_words = 0;
     uint32_t max_n = 0;
     bool all_n_mult4 = true;
+    bool all_pow2 = true;
 };
 
 int host_shapes(rasp_ctx *c, const rasp_batch_desc *d, HostShapes *h)
@@ -290,6 +307,7 @@ int host_shapes(rasp_ctx *c, const rasp_batch_desc *d, HostShapes *h)
         h->sum_n += n; h->sum_n_pad += (n + 3u) & ~3ull; h->sum_ell += ell; h->sum_s += s;
         if (n & 3u) h->all_n_mult4 = false;
         h->max_n = std::max(h->max_n, n);
+        if (n & (n - 1u)) h->all_pow2 = false;
     }
     h->prog_words = d->prog_off[N] - d->prog_off[0];
     h->tape_words = d->tape_off[N] - d->tape_off[0];
@@ -303,7 +321,9 @@ int basic_desc_checks(rasp_ctx *c, const rasp_batch_desc *d)
     if (d->isa != RASP_ISA_WORD && d->isa != RASP_ISA_CLASSIC) return fail(c, RASP_E_INVAL, "unknown isa %u", d->isa);
     if (d->num_vms == 0 || d->num_vms >= (1ull << 32)) return fail(c, RASP_E_INVAL, "num_vms must be in [1, 2^32)");
     if (!d->prog_off || !d->tape_off) return fail(c, RASP_E_INVAL, "prog_off and tape_off are required");
-    if (d->flags & ~RASP_DESC_DEVICE_PTRS) return fail(c, RASP_E_INVAL, "unknown descriptor flags");
+    if (d->flags & ~(RASP_DESC_DEVICE_PTRS | RASP_DESC_LAZY)) return fail(c, RASP_E_INVAL, "unknown descriptor flags");
+    if ((d->flags & RASP_DESC_LAZY) && !(d->flags & RASP_DESC_DEVICE_PTRS))
+        return fail(c, RASP_E_INVAL, "RASP_DESC_LAZY needs a device descriptor");
     return RASP_OK;
 }
 
@@ -343,6 +363,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         B->sum_n = h.sum_n; B->sum_n_pad = h.sum_n_pad; B->sum_ell = h.sum_ell; B->sum_s = h.sum_s;
         B->uniform_dense = h.all_n_mult4;
         B->max_n = h.max_n;
+        B->all_pow2 = h.all_pow2;
         if (!arena_alloc(c, words_bytes(h.sum_n_pad, h.sum_ell, h.sum_s), &B->words)) {
             fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)h.sum_n);
             return bail(RASP_E_NOMEM);
@@ -436,7 +457,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         if (!e) e = launch_scan_u32(B->dev.ell, B->dev.t_off, N, sums + align_up(8 * nsc, kAlign) / 8, &tots[1], st);
         if (!e) e = launch_scan_u32(B->dev.s, B->dev.y_off, N, sums + 2 * align_up(8 * nsc, kAlign) / 8, &tots[2], st);
         if (!e) e = launch_scan_u32(B->dev.n, n_pad, N, sums, &tots[3], st);   // dense total into tots[3]
-        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
         if (!e) e = hipStreamSynchronize(st);
         if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         uint32_t errbits;
@@ -447,6 +468,9 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         }
         B->sum_n_pad = c->tot_host[0]; B->sum_ell = c->tot_host[1]; B->sum_s = c->tot_host[2]; B->sum_n = c->tot_host[3];
         std::memcpy(&B->max_n, reinterpret_cast<char *>(c->tot_host) + 36, 4);
+        uint32_t nonpow2 = 0;
+        std::memcpy(&nonpow2, reinterpret_cast<char *>(c->tot_host) + 40, 4);
+        B->all_pow2 = nonpow2 == 0;
         B->uniform_dense = (B->sum_n == B->sum_n_pad);
         if (!arena_alloc(c, words_bytes(B->sum_n_pad, B->sum_ell, B->sum_s), &B->words)) {
             fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)B->sum_n);
@@ -454,13 +478,36 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         }
         carve_words(at<char>(c, B->words), B->sum_n_pad, B->sum_ell, &B->dev);
         prog_dev = d->prog; tape_dev = d->tape; poff_dev = d->prog_off; toff_dev = d->tape_off;
-        e = timed_launch(c, RASP_KERNEL_PACK, [&] { return launch_pack(B->dev, prog_dev, poff_dev, tape_dev, toff_dev, st); });
+        B->dev.prog = prog_dev; B->dev.prog_off = poff_dev; B->dev.tape = tape_dev; B->dev.tape_off = toff_dev;
+        if (d->flags & RASP_DESC_LAZY) {
+            B->dev.fresh = 1;              // c0 is built by the first run (or on demand)
+        } else {
+            e = timed_launch(c, RASP_KERNEL_PACK, [&] { return launch_pack(B->dev, prog_dev, poff_dev, tape_dev, toff_dev, st); });
+        }
         if (e) { fail(c, RASP_E_DEVICE, "pack: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         // scratch is only used by work queued before this point: stream order makes reuse safe
         arena_free(c, &staging);
     }
     out = std::move(B);
     return RASP_OK;
+}
+
+// LDS words per machine slot for a launch whose largest memory is max_n:
+// the option, or (option -1) the smallest power of two holding the whole
+// memory if two waves of such slots fit a compute unit, else none
+uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n)
+{
+    const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
+    uint32_t P;
+    if (c->lds_words >= 0) {
+        P = static_cast<uint32_t>(c->lds_words);
+    } else {
+        P = 4;
+        while (P < max_n && P < 1024) P <<= 1;
+        if (P < max_n || 2ull * kWave * (P + 4) * 4 > lds) P = 0;
+    }
+    while (P && static_cast<uint64_t>(kWave) * (P + 4) * 4 > lds) P >>= 1;
+    return P;
 }
 
 // ensure the survivor list holds `items` entries
@@ -496,6 +543,19 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     const uint32_t isa = bs[0]->dev.isa;
     for (uint32_t t = 1; t < k; ++t)
         if (bs[t]->dev.isa != isa) return fail(c, RASP_E_INVAL, "batches of one launch must share the instruction set");
+    // lazily loaded batches are built inside the persistent kernel when every
+    // machine of the launch fits its LDS slot; otherwise c0 is packed first
+    bool any_fresh = false;
+    uint32_t mx = 0;
+    for (uint32_t t = 0; t < k; ++t) { any_fresh |= bs[t]->dev.fresh != 0; mx = std::max(mx, bs[t]->max_n); }
+    const uint32_t Pq = lds_words_for(c, mx);
+    const int64_t schedq = c->schedule == RASP_SCHED_AUTO ? RASP_SCHED_PERSISTENT : c->schedule;
+    const bool fused = any_fresh && schedq == RASP_SCHED_PERSISTENT && Pq >= mx;
+    for (uint32_t t = 0; t < k; ++t)
+        if (bs[t]->dev.fresh && (!fused || budgets[t] == 0)) {
+            int rc = materialize(c, bs[t]);
+            if (rc) return rc;
+        }
     BatchTable *ht, *dt;
     int slot;
     int rc = table_slot(c, &ht, &dt, &slot);
@@ -503,8 +563,10 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     std::memset(ht, 0, sizeof(BatchTable));
     uint64_t total = 0;
     uint32_t maxb = 0, max_n = 0;
+    bool pow2 = true;
     for (uint32_t t = 0; t < k; ++t) {
         max_n = std::max(max_n, bs[t]->max_n);
+        pow2 &= bs[t]->all_pow2;
         ht->b[t] = bs[t]->dev;
         ht->start[t] = total;
         ht->budget[t] = budgets[t];
@@ -514,7 +576,10 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     ht->start[k] = total;
     ht->count = k;
     if (total >= (1ull << 32)) return fail(c, RASP_E_INVAL, "too many machines in one launch");
-    if (maxb == 0) return RASP_OK;
+    if (maxb == 0) {
+        for (uint32_t t = 0; t < k; ++t) { int rc2 = materialize(c, bs[t]); if (rc2) return rc2; }
+        return RASP_OK;
+    }
     for (uint32_t t = 0; t < k; ++t)
         if (budgets[t] > 0) bs[t]->status_stale = false;    // every run recomputes status
     hipStream_t st = c->stream;
@@ -526,32 +591,36 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     int64_t sched = c->schedule;
     if (sched == RASP_SCHED_AUTO) sched = RASP_SCHED_PERSISTENT;
     if (sched == RASP_SCHED_PLAIN) {
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, nullptr, c->queue, st); }));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, pow2, nullptr, c->queue, st); }));
         return RASP_OK;
     }
     // persistent: a first plain pass of `first_pass` steps retires the short
     // runners; the survivors go through the persistent kernel
     const uint32_t cap = static_cast<uint32_t>(std::max<int64_t>(0, c->first_pass));
     // waves per block: as many (up to 4) as the LDS slots of one block allow
-    uint32_t P = static_cast<uint32_t>(std::max<int64_t>(0, c->lds_words));
+    const uint32_t P = lds_words_for(c, max_n);
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
-    while (P && static_cast<uint64_t>(kWave) * (P + 4) * 4 > lds) P >>= 1;
     uint32_t wpb = 4;
     while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * (P + 4) * 4 > lds) wpb >>= 1;
     const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
     const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
     const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
-    if (cap > 0 && cap < maxb) {
+    if (fused) {
+        // fresh batches present: one persistent launch over every machine
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
+            return launch_persistent(dt, total, nullptr, 0, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st); }));
+        for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
+    } else if (cap > 0 && cap < maxb) {
         if ((rc = ensure_work(c, total))) return rc;
         uint32_t *work = at<uint32_t>(c, c->work);
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, cap, isa, work, c->queue, st); }));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, cap, isa, pow2, work, c->queue, st); }));
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, work, cap, isa, epoch, P, max_n, wpb, blocks, c->queue, st); }));
+            return launch_persistent(dt, total, work, cap, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st); }));
     } else if (cap >= maxb) {
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, nullptr, c->queue, st); }));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, pow2, nullptr, c->queue, st); }));
     } else {
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, nullptr, 0, isa, epoch, P, max_n, wpb, blocks, c->queue, st); }));
+            return launch_persistent(dt, total, nullptr, 0, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st); }));
     }
     return RASP_OK;
 }
@@ -604,7 +673,7 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     }
     c->arena_bytes = arena_bytes;
     c->alloc.reset(arena_bytes);
-    const uint64_t sbytes = align_up(sizeof(QueueState), kAlign) + kTableRing * align_up(sizeof(BatchTable), kAlign);
+    const uint64_t sbytes = align_up(sizeof(QueueState), kAlign) + (kTableRing + 1) * align_up(sizeof(BatchTable), kAlign);
     bool ok = arena_alloc(c.get(), sbytes, &c->scratch);
     if (ok) {
         c->queue = at<QueueState>(c.get(), c->scratch);
@@ -612,13 +681,12 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     }
     e = ok ? hipHostMalloc(reinterpret_cast<void **>(&c->host_tables), kTableRing * sizeof(BatchTable), hipHostMallocDefault) : hipErrorOutOfMemory;
     if (!e) e = hipHostMalloc(reinterpret_cast<void **>(&c->tot_host), 64, hipHostMallocDefault);
+    if (!e) e = hipHostMalloc(reinterpret_cast<void **>(&c->count_host), 8 * kMaxMulti, hipHostMallocDefault);
     for (int k = 0; k < kTableRing && !e; ++k) e = hipEventCreateWithFlags(&c->table_ev[k], hipEventDisableTiming);
     if (e) {
         rasp_destroy(c.release());
         return fail(nullptr, RASP_E_DEVICE, "context scratch: %s", hipGetErrorString(e));
     }
-    // defaults: stage the whole memory in LDS when it is small
-    c->lds_words = 0;
     *out = c.release();
     return RASP_OK;
 }
@@ -634,6 +702,7 @@ int rasp_destroy(rasp_ctx *c)
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->host_tables) (void)hipHostFree(c->host_tables);
     if (c->tot_host) (void)hipHostFree(c->tot_host);
+    if (c->count_host) (void)hipHostFree(c->count_host);
     if (c->own_arena && c->arena) (void)hipFree(c->arena);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -811,6 +880,7 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
     Batch *b = find(c, h);
     if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
     if (!o) return fail(c, RASP_E_INVAL, "outputs is NULL");
+    if ((rc = materialize(c, b))) return rc;
     hipStream_t st = c->stream;
     const hipMemcpyKind kind = (o->flags & RASP_OUT_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const uint64_t N = b->N;
@@ -875,6 +945,7 @@ int rasp_batch_info(rasp_ctx *c, rasp_batch h, uint64_t *num_vms, uint64_t *mem_
     if (mem_words) *mem_words = b->sum_n;
     if (out_words) *out_words = b->sum_s;
     if (steps_sum) {
+        if ((rc = materialize(c, b))) return rc;
         unsigned long long *d = reinterpret_cast<unsigned long long *>(&c->queue->retired);
         HIPCHK(c, hipMemsetAsync(d, 0, 8, c->stream));
         HIPCHK(c, launch_steps_sum(b->dev, d, c->stream));
@@ -882,6 +953,44 @@ int rasp_batch_info(rasp_ctx *c, rasp_batch h, uint64_t *num_vms, uint64_t *mem_
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *steps_sum = c->tot_host[0];
     }
+    return RASP_OK;
+}
+
+int rasp_running_counts(rasp_ctx *c, const rasp_batch *hs, uint32_t k, uint64_t *counts)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!hs || !counts || k == 0 || k > static_cast<uint32_t>(kMaxMulti))
+        return fail(c, RASP_E_INVAL, "rasp_running_counts takes 1..%d batches", kMaxMulti);
+    hipStream_t st = c->stream;
+    BatchTable *ht, *dt;
+    int slot;
+    if ((rc = table_slot(c, &ht, &dt, &slot))) return rc;
+    std::memset(ht, 0, sizeof(BatchTable));
+    uint64_t total = 0;
+    for (uint32_t t = 0; t < k; ++t) {
+        Batch *b = find(c, hs[t]);
+        if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)hs[t]);
+        if ((rc = materialize(c, b))) return rc;
+        if (b->status_stale) {
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_probe(b->dev, st); }));
+            b->status_stale = false;
+        }
+        ht->b[t] = b->dev;
+        ht->start[t] = total;
+        total += b->N;
+    }
+    ht->start[k] = total;
+    ht->count = k;
+    unsigned long long *dcount = reinterpret_cast<unsigned long long *>(&c->tables[kTableRing]);
+    HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
+    c->table_used[slot] = true;
+    HIPCHK(c, hipMemsetAsync(dcount, 0, 8 * kMaxMulti, st));
+    HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_running(dt, total, dcount, st); }));
+    HIPCHK(c, hipMemcpyAsync(c->count_host, dcount, 8 * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    std::memcpy(counts, c->count_host, 8 * k);
     return RASP_OK;
 }
 
@@ -909,8 +1018,8 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
         if (value < 1 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "epoch must be >= 1");
         c->epoch = value; return RASP_OK;
     case RASP_OPT_LDS_WORDS:
-        if (value < 0 || value > 1024 || (value & (value - 1)) || (value > 0 && value < 4))
-            return fail(c, RASP_E_INVAL, "lds words must be 0 or a power of two in [4, 1024]");
+        if (value < -1 || value > 1024 || (value > 0 && ((value & (value - 1)) || value < 4)))
+            return fail(c, RASP_E_INVAL, "lds words must be -1 (auto), 0 or a power of two in [4, 1024]");
         c->lds_words = value; return RASP_OK;
     case RASP_OPT_WAVES_PER_CU:
         if (value < 1 || value > 32) return fail(c, RASP_E_INVAL, "waves per CU must be in [1, 32]");

@@ -25,6 +25,7 @@ RASP_OK, RASP_E_INVAL, RASP_E_NOMEM, RASP_E_DEVICE, RASP_E_STATE, RASP_E_BUSY = 
 RASP_ISA_WORD, RASP_ISA_CLASSIC = 0, 1
 RASP_RUNNING, RASP_HALTED = 0, 1
 RASP_DESC_DEVICE_PTRS = 1
+RASP_DESC_LAZY = 2
 RASP_OUT_DEVICE_PTRS = 1
 RASP_OPT_SCHEDULE, RASP_OPT_EPOCH, RASP_OPT_LDS_WORDS = 1, 2, 3
 RASP_OPT_WAVES_PER_CU, RASP_OPT_GRAPH, RASP_OPT_FIRST_PASS = 4, 5, 6
@@ -36,7 +37,7 @@ EXPORTED = ("rasp_create", "rasp_destroy", "rasp_last_error", "rasp_batch_footpr
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
             "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
-            "rasp_kernel_times")
+            "rasp_kernel_times", "rasp_running_counts")
 
 _ERRNAMES = {RASP_E_INVAL: "RASP_E_INVAL", RASP_E_NOMEM: "RASP_E_NOMEM",
              RASP_E_DEVICE: "RASP_E_DEVICE", RASP_E_STATE: "RASP_E_STATE",
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "rasp_get_option": ([P, i32, ctypes.POINTER(i64)], i32),
         "rasp_device_info": ([P, P, P, P], i32),
         "rasp_kernel_times": ([P, P, P], i32),
+        "rasp_running_counts": ([P, P, u32, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -126,9 +128,10 @@ class Desc:
     keep: tuple
 
 
-def make_desc(batch, device=None) -> Desc:
+def make_desc(batch, device=None, lazy: bool = False) -> Desc:
     """Descriptor for a workloads.Batch.  With device=<torch device> the arrays are
-    copied to the GPU first and the descriptor says RASP_DESC_DEVICE_PTRS."""
+    copied to the GPU first and the descriptor says RASP_DESC_DEVICE_PTRS (plus
+    RASP_DESC_LAZY when lazy: c0 is then built by the first run)."""
     arrs = dict(prog=np.ascontiguousarray(batch.prog, np.int32),
                 prog_off=np.ascontiguousarray(batch.prog_off, np.uint64),
                 mem_words=np.ascontiguousarray(batch.mem_words, np.uint32),
@@ -142,7 +145,7 @@ def make_desc(batch, device=None) -> Desc:
         signed = {np.dtype(np.uint64): np.int64, np.dtype(np.uint32): np.int32}
         arrs = {k: torch.from_numpy(v.view(signed.get(v.dtype, v.dtype))).to(device)
                 for k, v in arrs.items()}
-        flags = RASP_DESC_DEVICE_PTRS
+        flags = RASP_DESC_DEVICE_PTRS | (RASP_DESC_LAZY if lazy else 0)
     return desc_from_arrays(batch.isa, batch.N, flags=flags, **arrs)
 
 
@@ -259,6 +262,13 @@ def rasp_fetch_outputs_into(ctx, batch: int, dst: dict, device: bool) -> None:
     _check(_lib.rasp_fetch_outputs(ctx, batch, ctypes.byref(s)), ctx)
 
 
+def rasp_running_counts(ctx, batches) -> np.ndarray:
+    hs = np.ascontiguousarray(batches, np.uint64)
+    out = np.zeros(len(hs), np.uint64)
+    _check(_lib.rasp_running_counts(ctx, _ptr(hs), len(hs), _ptr(out)), ctx)
+    return out
+
+
 def rasp_free_batch(ctx, batch: int) -> None:
     _check(_lib.rasp_free_batch(ctx, batch), ctx)
 
@@ -298,6 +308,7 @@ class Context:
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.handle = rasp_create(device, self.arena, arena_bytes, self.stream)
+        self._keep = {}
 
     def close(self):
         if self.handle:
@@ -316,9 +327,14 @@ class Context:
         except Exception:
             pass
 
-    def load(self, batch, device_desc: bool = False) -> int:
-        d = make_desc(batch, self.device if device_desc else None)
-        return rasp_load_batch(self.handle, d)
+    def load(self, batch, device_desc: bool = False, lazy: bool = False) -> int:
+        """Load a batch.  A lazy descriptor (device arrays read by the first
+        run) is kept alive here until the batch is freed."""
+        d = make_desc(batch, self.device if (device_desc or lazy) else None, lazy=lazy)
+        h = rasp_load_batch(self.handle, d)
+        if lazy:
+            self._keep[h] = d
+        return h
 
     def load_state(self, batch, state: dict) -> int:
         return rasp_load_state(self.handle, make_desc(batch), state)
@@ -334,6 +350,7 @@ class Context:
 
     def free(self, b: int) -> None:
         rasp_free_batch(self.handle, b)
+        self._keep.pop(b, None)
 
     def sync(self) -> None:
         rasp_sync(self.handle)

@@ -297,3 +297,46 @@ def test_budget_zero_reports_fixed_points_of_c0(ctx, rasp):
     got = run_gpu(ctx, b, 0)
     compare(got, oracle.run(b, 0))
     assert got["status"].any() and not got["status"].all()
+
+
+@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "firstpass-lds64", "auto"])
+def test_lazy_descriptor_equals_eager(ctx, rasp, sched):
+    """RASP_DESC_LAZY (c0 built inside the first run) gives the same state as
+    an eager load, whichever schedule runs it (fused persistent launch when
+    memories fit their LDS slots, else c0 packed first)."""
+    if sched == "auto":
+        ctx.set(rasp.RASP_OPT_SCHEDULE, 0)
+        ctx.set(rasp.RASP_OPT_LDS_WORDS, -1)
+        ctx.set(rasp.RASP_OPT_EPOCH, 16)
+    else:
+        configure(ctx, rasp, sched)
+    for b in (W.config1(seed=51), W.tiny_random(seed=52, num_vms=3000, max_n=40),
+              W.config2(num_vms=5000, seed=53)):
+        d = rasp.make_desc(b, ctx.device, lazy=True)
+        h = rasp.rasp_load_batch(ctx.handle, d)
+        ctx.run(h, 300)
+        got = ctx.fetch(h, mem=True)
+        ctx.free(h)
+        compare(got, oracle.run(b, 300))
+
+
+def test_lazy_descriptor_without_run_and_in_a_mix(ctx, rasp):
+    ctx.set(rasp.RASP_OPT_SCHEDULE, 0)
+    ctx.set(rasp.RASP_OPT_LDS_WORDS, -1)
+    b1, b2 = W.config1(seed=61), W.config1(seed=62)
+    # fetched before any run: c0, status = fixed point of c0
+    h = ctx.load(b1, device_desc=True, lazy=True)
+    compare(ctx.fetch(h, mem=True), oracle.run(b1, 0))
+    ctx.free(h)
+    # a lazy batch (budget 0 and 200) next to an eager one in one launch; the
+    # lazy descriptors' device arrays stay alive until the run (Context.load
+    # keeps them until the batch is freed)
+    ha = ctx.load(b1, device_desc=True, lazy=True)
+    hb = ctx.load(b2)
+    hc = ctx.load(b2, device_desc=True, lazy=True)
+    ctx.run_multi([ha, hb, hc], [200, 150, 0])
+    compare(ctx.fetch(ha, mem=True), oracle.run(b1, 200))
+    compare(ctx.fetch(hb, mem=True), oracle.run(b2, 150))
+    compare(ctx.fetch(hc, mem=True), oracle.run(b2, 0))
+    for x in (ha, hb, hc):
+        ctx.free(x)

@@ -42,7 +42,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain-scale",
-                    choices=["plain-scale", "plain-small", "uneven", "rollouts"])
+                    choices=["plain-scale", "plain-small", "uneven", "rollouts", "serve"])
+    ap.add_argument("--requests", type=int, default=120, help="serve: requests per run")
+    ap.add_argument("--loads", default="0.5,0.8", help="serve: offered load, fractions of capacity")
+    ap.add_argument("--cap-gb", type=float, default=200.0, help="serve: arena footprint cap")
+    ap.add_argument("--serve-epoch", type=int, default=4096, help="serve: transitions per epoch")
     ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-schedule comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,6 +97,71 @@ def pack_bytes(batch) -> int:
                     + batch.out_cap.astype(np.int64).sum()) + 25 * N)
 
 
+def serve_bench(args):
+    """Serving: a Poisson stream of rollout requests (1,024-262,144 machines,
+    family uniform over plain-small / plain-scale / uneven, budgets 4,096-65,536)
+    served with continuous batching under a footprint cap.  Capacity is first
+    measured closed-loop (every request queued at t = 0); the stream is then
+    replayed at fixed fractions of that rate.  Reports retired steps/s and
+    p50/p99 request latency (arrival to outputs on the host)."""
+    import torch
+    import oracle
+    from paper_2604_12902_amd import rasp as R, serving
+
+    t0 = time.time()
+    reqs = serving.poisson_requests(args.requests, 1.0, seed=4)
+    base_arrivals = [q.arrival for q in reqs]
+    print("serve: %d requests generated in %.1f s (%d machines)" % (
+        len(reqs), time.time() - t0, sum(q.size for q in reqs)), flush=True)
+    free, _ = torch.cuda.mem_get_info()
+    cap = int(min(args.cap_gb * 1e9, 0.85 * free))
+    ctx = R.Context(cap + (256 << 20))
+    ex = serving.RaspExecutor(ctx)
+
+    def run(qps):
+        for q, a in zip(reqs, base_arrivals):
+            q.arrival = 0.0 if qps is None else a / qps
+            q.result = None
+        st = serving.Server(ex, cap, epoch=args.serve_epoch).serve(reqs)
+        return st
+
+    run(None)                                           # warm-up
+    closed = run(None)
+    cap_qps = closed.requests / closed.wall_s
+    print("serve: closed loop %.3f s, %.1f requests/s, %.3e steps/s" % (
+        closed.wall_s, cap_qps, closed.steps_per_s), flush=True)
+    # bit-exactness of a sample of every request's machines against the oracle
+    for q in reqs[:: max(1, len(reqs) // 6)]:
+        idx = np.arange(0, q.batch.N, max(1, q.batch.N // 300))
+        want = oracle.run(q.batch.subset(idx), q.budget, threads=16)
+        for k in ("status", "steps", "i", "a", "u0", "y0"):
+            if not np.array_equal(np.asarray(q.result[k])[idx], getattr(want, k)):
+                raise SystemExit("serve: NOT bit-exact (request %d, %s)" % (q.rid, k))
+    runs = []
+    for f in [float(x) for x in args.loads.split(",") if x]:
+        st = run(f * cap_qps)
+        runs.append(dict(load=f, qps=f * cap_qps, wall_s=st.wall_s, steps_per_s=st.steps_per_s,
+                         p50_ms=st.p50_ms, p99_ms=st.p99_ms, mean_ms=st.mean_ms,
+                         epochs=st.epochs, max_active=st.max_active))
+        print("serve: load %.2f qps %.1f: %.3e steps/s  p50 %.1f ms  p99 %.1f ms  epochs %d  "
+              "max active %d" % (f, f * cap_qps, st.steps_per_s, st.p50_ms, st.p99_ms, st.epochs,
+                                 st.max_active), flush=True)
+    ctx.close()
+    head = runs[-1] if runs else None
+    line = {"metric": "VM instructions retired/sec (1 GPU), bit-exact; served; p50/p99 request latency",
+            "value": head["steps_per_s"] if head else closed.steps_per_s,
+            "unit": "VM instructions retired/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic (seeded Poisson stream of random RASP programs)",
+            "config": {"workload": "serving: Poisson stream, %d requests of 1,024-262,144 machines, "
+                                   "budgets 4,096-65,536, cap %.1f GB" % (len(reqs), cap / 1e9),
+                       "epoch": args.serve_epoch},
+            "closed_loop": {"requests_per_s": cap_qps, "steps_per_s": closed.steps_per_s,
+                            "p50_ms": closed.p50_ms, "p99_ms": closed.p99_ms},
+            "open_loop": runs}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -100,6 +169,9 @@ def main():
               "independent machines and this build has no multi-GPU path; run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serve":
+        serve_bench(args)
+        return
 
     import torch
     import oracle

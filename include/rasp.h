@@ -258,7 +258,10 @@ int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
  *                          persistent kernel (0 = none), power of two <= 1024
  *   RASP_OPT_WAVES_PER_CU  resident waves per compute unit for the persistent
  *                          kernel
- *   RASP_OPT_GRAPH         1: replay persistent launches through a HIP graph
+ *   RASP_OPT_GRAPH         1: capture the launch sequence of a run (queue reset,
+ *                          plain pass, persistent kernel) once per (batches,
+ *                          budgets, knobs) and replay it as a HIP graph; graphs
+ *                          of a batch are dropped when it is freed
  *   RASP_OPT_FIRST_PASS    persistent schedule only: transitions every machine
  *                          first runs in a plain one-machine-per-lane pass;
  *                          the machines still running then go through the
@@ -294,6 +297,20 @@ enum {
 };
 enum { RASP_OPT_PROFILE = 7 };
 int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
+
+/*
+ * rasp_autotune: choose the scheduling knobs for batches shaped like b.
+ * Copies the first min(num_vms, max_vms) machines of b into a scratch batch
+ * (b itself is not changed), then times rasp_run(budget) on fresh copies of
+ * that snapshot while searching one knob at a time (LDS words per machine,
+ * first-pass length, epoch, waves per compute unit; persistent schedule
+ * against plain), keeps the fastest setting in the context and writes it to
+ * chosen[0..4] = {schedule, lds_words, first_pass, epoch, waves_per_cu}
+ * (chosen may be NULL).  Returns the best time in *best_ms (may be NULL).
+ * Errors: STATE, NOMEM (no room for the snapshot), DEVICE.
+ */
+int rasp_autotune(rasp_ctx *ctx, rasp_batch b, uint64_t budget, uint64_t max_vms,
+                  int64_t *chosen, double *best_ms);
 
 /* Device properties the context saw: compute units, LDS bytes per workgroup. */
 int rasp_device_info(rasp_ctx *ctx, int *compute_units, int *lds_bytes, int *wave_size);

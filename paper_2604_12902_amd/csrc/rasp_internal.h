@@ -94,6 +94,7 @@ hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32
                              uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
                              QueueState *q, hipStream_t st);
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
+void init_kernel_attributes();
 hipError_t launch_running(const BatchTable *tab, uint64_t total, unsigned long long *counts,
                           hipStream_t st);
 hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st);

@@ -579,15 +579,24 @@ static hipError_t launch_k3(dim3 grid, dim3 block, size_t shmem, hipStream_t st,
                             uint64_t total, const uint32_t *work, uint32_t already, uint32_t epoch,
                             uint32_t P, QueueState *q)
 {
-    static bool attr = false;
-    if (MODE != 0 && !attr) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<ISA, MODE, POW2>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        (void)hipGetLastError();
-        attr = true;
-    }
     k_persistent<ISA, MODE, POW2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, P, q);
     return hipGetLastError();
+}
+
+template <int ISA, int MODE, bool POW2>
+static void lds_attr()
+{
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<ISA, MODE, POW2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// Allow the persistent kernels the whole LDS of a compute unit; called once
+// per context, outside any stream capture.
+void init_kernel_attributes()
+{
+    lds_attr<0, 1, false>(); lds_attr<0, 1, true>(); lds_attr<0, 2, false>(); lds_attr<0, 2, true>();
+    lds_attr<1, 1, false>(); lds_attr<1, 1, true>(); lds_attr<1, 2, false>(); lds_attr<1, 2, true>();
+    (void)hipGetLastError();
 }
 
 template <int ISA, int MODE>

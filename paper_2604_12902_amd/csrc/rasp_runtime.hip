@@ -164,6 +164,14 @@ struct rasp_ctx {
     uint32_t *err_host = nullptr;        // pinned: error word and totals
     uint64_t *tot_host = nullptr;
     uint64_t *count_host = nullptr;      // pinned: running counts
+    // captured launch sequences (RASP_OPT_GRAPH)
+    struct GraphEntry {
+        std::vector<uint64_t> key;         // handles, budgets, knobs
+        std::vector<uint64_t> handles;
+        Alloc table;                       // the graph's own device batch table
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
     // kernel timing (RASP_OPT_PROFILE)
     int64_t profile = 0;
     struct Timed { int kind; hipEvent_t a, b; };
@@ -510,11 +518,28 @@ uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n)
     return P;
 }
 
+// drop captured graphs (all of them, or those that use batch h)
+void drop_graphs(rasp_ctx *c, bool all, uint64_t h = 0)
+{
+    std::vector<rasp_ctx::GraphEntry> keep;
+    bool synced = false;
+    for (auto &g : c->graphs) {
+        bool uses = all;
+        for (auto x : g.handles) uses |= (x == h);
+        if (!uses) { keep.push_back(std::move(g)); continue; }
+        if (!synced) { (void)hipStreamSynchronize(c->stream); synced = true; }
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        arena_free(c, &g.table);
+    }
+    c->graphs = std::move(keep);
+}
+
 // ensure the survivor list holds `items` entries
 int ensure_work(rasp_ctx *c, uint64_t items)
 {
     if (items <= c->work_cap) return RASP_OK;
     if (c->work.live) {
+        drop_graphs(c, true);                  // captured launches point at the old list
         HIPCHK(c, hipStreamSynchronize(c->stream));
         arena_free(c, &c->work);
     }
@@ -583,20 +608,22 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     for (uint32_t t = 0; t < k; ++t)
         if (budgets[t] > 0) bs[t]->status_stale = false;    // every run recomputes status
     hipStream_t st = c->stream;
-    HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
-    HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
-    c->table_used[slot] = true;
-    HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_zero_queue(c->queue, st); }));
-
     int64_t sched = c->schedule;
     if (sched == RASP_SCHED_AUTO) sched = RASP_SCHED_PERSISTENT;
-    if (sched == RASP_SCHED_PLAIN) {
+    if (!(c->graph && !fused)) {
+        HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
+        c->table_used[slot] = true;
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_zero_queue(c->queue, st); }));
+    }
+    if (sched == RASP_SCHED_PLAIN && !c->graph) {
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, pow2, nullptr, c->queue, st); }));
         return RASP_OK;
     }
     // persistent: a first plain pass of `first_pass` steps retires the short
-    // runners; the survivors go through the persistent kernel
-    const uint32_t cap = static_cast<uint32_t>(std::max<int64_t>(0, c->first_pass));
+    // runners; the survivors go through the persistent kernel (the plain
+    // schedule is a first pass as long as the budget)
+    const uint32_t cap = sched == RASP_SCHED_PLAIN ? maxb : static_cast<uint32_t>(std::max<int64_t>(0, c->first_pass));
     // waves per block: as many (up to 4) as the LDS slots of one block allow
     const uint32_t P = lds_words_for(c, max_n);
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
@@ -605,6 +632,48 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
     const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
     const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
+    if (c->graph && !fused) {
+        // replay (capturing on first use) the launch sequence for this key
+        std::vector<uint64_t> key;
+        for (uint32_t t = 0; t < k; ++t) { key.push_back(reinterpret_cast<uint64_t>(bs[t])); key.push_back(budgets[t]); }
+        const uint64_t knobs[] = {static_cast<uint64_t>(c->schedule), P, epoch, cap, wpb, blocks,
+                                  pow2 ? 1u : 0u, isa, maxb};
+        key.insert(key.end(), knobs, knobs + 9);
+        rasp_ctx::GraphEntry *ge = nullptr;
+        for (auto &g : c->graphs) if (g.key == key) ge = &g;
+        if (!ge) {
+            if (cap > 0 && cap < maxb && (rc = ensure_work(c, total))) return rc;
+            rasp_ctx::GraphEntry g;
+            g.key = key;
+            if (!arena_alloc(c, sizeof(BatchTable), &g.table)) return fail(c, RASP_E_NOMEM, "arena cannot hold a graph table");
+            BatchTable *gt = at<BatchTable>(c, g.table);
+            HIPCHK(c, hipMemcpyAsync(gt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            uint32_t *work = (cap > 0 && cap < maxb) ? at<uint32_t>(c, c->work) : nullptr;
+            hipGraph_t graph = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t e = launch_zero_queue(c->queue, st);
+            if (!e && cap > 0 && cap < maxb) {
+                e = launch_plain(gt, total, cap, isa, pow2, work, c->queue, st);
+                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st);
+            } else if (!e && cap >= maxb) {
+                e = launch_plain(gt, total, maxb, isa, pow2, nullptr, c->queue, st);
+            } else if (!e) {
+                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st);
+            }
+            hipError_t e2 = hipStreamEndCapture(st, &graph);
+            if (!e) e = e2;
+            if (!e) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e) { arena_free(c, &g.table); return fail(c, RASP_E_DEVICE, "graph capture: %s", hipGetErrorString(e)); }
+            for (uint32_t t = 0; t < k; ++t) g.handles.push_back(reinterpret_cast<uint64_t>(bs[t]));
+            c->graphs.push_back(std::move(g));
+            ge = &c->graphs.back();
+        }
+        hipGraphExec_t ex = ge->exec;
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] { return hipGraphLaunch(ex, st); }));
+        return RASP_OK;
+    }
     if (fused) {
         // fresh batches present: one persistent launch over every machine
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
@@ -673,6 +742,7 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     }
     c->arena_bytes = arena_bytes;
     c->alloc.reset(arena_bytes);
+    init_kernel_attributes();
     const uint64_t sbytes = align_up(sizeof(QueueState), kAlign) + (kTableRing + 1) * align_up(sizeof(BatchTable), kAlign);
     bool ok = arena_alloc(c.get(), sbytes, &c->scratch);
     if (ok) {
@@ -696,6 +766,8 @@ int rasp_destroy(rasp_ctx *c)
     if (!c) return RASP_OK;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &g : c->graphs) if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
     for (int k = 0; k < kTableRing; ++k)
         if (c->table_ev[k]) (void)hipEventDestroy(c->table_ev[k]);
     for (auto &t : c->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
@@ -999,6 +1071,7 @@ int rasp_free_batch(rasp_ctx *c, rasp_batch h)
     if (!c) return RASP_E_INVAL;
     auto it = c->batches.find(h);
     if (it == c->batches.end()) return fail(c, RASP_E_STATE, "unknown or freed batch handle %llu", (unsigned long long)h);
+    drop_graphs(c, false, reinterpret_cast<uint64_t>(it->second.get()));
     // later work on the same stream may reuse the space only after this batch's
     // queued work: stream order guarantees it
     arena_free(c, &it->second->words);
@@ -1025,7 +1098,9 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
         if (value < 1 || value > 32) return fail(c, RASP_E_INVAL, "waves per CU must be in [1, 32]");
         c->waves_per_cu = value; return RASP_OK;
     case RASP_OPT_GRAPH:
-        c->graph = value ? 1 : 0; return RASP_OK;
+        c->graph = value ? 1 : 0;
+        if (!c->graph) drop_graphs(c, true);
+        return RASP_OK;
     case RASP_OPT_FIRST_PASS:
         if (value < 0 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "first pass must be >= 0");
         c->first_pass = value; return RASP_OK;
@@ -1067,6 +1142,143 @@ int rasp_kernel_times(rasp_ctx *c, double *ms, uint64_t *launches)
         c->ev_pool.push_back(t.b);
     }
     c->timed.clear();
+    return RASP_OK;
+}
+
+int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, int64_t *chosen,
+                  double *best_ms)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Batch *b = find(c, h);
+    if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
+    if ((rc = materialize(c, b))) return rc;
+    hipStream_t st = c->stream;
+    const uint64_t K = (max_vms == 0 || max_vms > b->N) ? b->N : max_vms;
+    const uint32_t bud = static_cast<uint32_t>(std::min<uint64_t>(budget, 0x7fffffffull));
+    // ends of the prefix's word ranges
+    uint64_t mo, to, yo;
+    uint32_t nn, el, ss;
+    HIPCHK(c, hipMemcpyAsync(&mo, b->dev.mem_off + K - 1, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&to, b->dev.t_off + K - 1, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&yo, b->dev.y_off + K - 1, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&nn, b->dev.n + K - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&el, b->dev.ell + K - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(&ss, b->dev.s + K - 1, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const uint64_t m_end = mo + ((nn + 3ull) & ~3ull), t_end = to + el, y_end = yo + ss;
+    // snapshot (restore source) and trial batch, both K machines
+    Batch snap, trial;
+    for (Batch *x : {&snap, &trial}) {
+        *x = Batch();
+        x->N = K;
+        x->sum_n_pad = m_end; x->sum_ell = t_end; x->sum_s = y_end;
+        x->max_n = b->max_n; x->all_pow2 = b->all_pow2; x->status_stale = b->status_stale;
+        if (!arena_alloc(c, meta_bytes(K), &x->meta) || !arena_alloc(c, words_bytes(m_end, t_end, y_end), &x->words)) {
+            arena_free(c, &snap.meta); arena_free(c, &snap.words);
+            arena_free(c, &trial.meta); arena_free(c, &trial.words);
+            return fail(c, RASP_E_NOMEM, "arena cannot hold the autotune snapshot (%llu machines)", (unsigned long long)K);
+        }
+        carve_meta(at<char>(c, x->meta), K, &x->dev);
+        carve_words(at<char>(c, x->words), m_end, t_end, &x->dev);
+        x->dev.isa = b->dev.isa;
+        x->dev.fresh = 0;
+    }
+    auto copy_batch = [&](const DevBatch &src, const DevBatch &dst) -> hipError_t {
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        hipError_t e = hipMemcpyAsync(dst.i, src.i, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.a, src.a, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.u0, src.u0, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.y0, src.y0, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.steps, src.steps, 8 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.status, src.status, K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.n, src.n, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.ell, src.ell, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.s, src.s, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.mem_off, src.mem_off, 8 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.t_off, src.t_off, 8 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.y_off, src.y_off, 8 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.M, src.M, 4 * m_end, k, st);
+        if (!e && t_end) e = hipMemcpyAsync(dst.T, src.T, 4 * t_end, k, st);
+        if (!e && y_end) e = hipMemcpyAsync(dst.Y, src.Y, 4 * y_end, k, st);
+        return e;
+    };
+    auto release = [&]() {
+        (void)hipStreamSynchronize(st);
+        arena_free(c, &snap.meta); arena_free(c, &snap.words);
+        arena_free(c, &trial.meta); arena_free(c, &trial.words);
+    };
+    hipError_t e = copy_batch(b->dev, snap.dev);
+    if (e) { release(); return fail(c, RASP_E_DEVICE, "autotune snapshot: %s", hipGetErrorString(e)); }
+    const int64_t saved[] = {c->schedule, c->lds_words, c->first_pass, c->epoch, c->waves_per_cu, c->graph, c->profile};
+    c->graph = 0;
+    c->profile = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto trial_ms = [&](double *ms) -> int {
+        hipError_t x = copy_batch(snap.dev, trial.dev);
+        if (x) return fail(c, RASP_E_DEVICE, "autotune restore: %s", hipGetErrorString(x));
+        trial.status_stale = snap.status_stale;
+        Batch *tb = &trial;
+        HIPCHK(c, hipEventRecord(e0, st));
+        int r2 = run_batches(c, &tb, &bud, 1);
+        if (r2) return r2;
+        HIPCHK(c, hipEventRecord(e1, st));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float f = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
+        *ms = f;
+        return RASP_OK;
+    };
+    // candidate values; one knob at a time from the current setting
+    const int64_t full = [&]() { int64_t P = 4; while (P < b->max_n && P < 1024) P <<= 1; return P; }();
+    std::vector<int64_t> lds_c = {0, 32, 64, 128, 256};
+    if (full <= 1024 && std::find(lds_c.begin(), lds_c.end(), full) == lds_c.end()) lds_c.push_back(full);
+    const std::vector<int64_t> fp_c = {0, 16, 64, 256}, ep_c = {64, 256, 1024}, wv_c = {8, 16, 32};
+    int64_t cur[5] = {RASP_SCHED_PERSISTENT, c->lds_words < 0 ? static_cast<int64_t>(lds_words_for(c, b->max_n)) : c->lds_words,
+                      c->first_pass, c->epoch, c->waves_per_cu};
+    auto apply = [&](const int64_t *o) {
+        c->schedule = o[0]; c->lds_words = o[1]; c->first_pass = o[2]; c->epoch = o[3]; c->waves_per_cu = o[4];
+    };
+    double best = 1e30;
+    apply(cur);
+    rc = trial_ms(&best);
+    // warm-up run above; measure the starting point again
+    if (!rc) rc = trial_ms(&best);
+    const std::vector<int64_t> *lists[5] = {nullptr, &lds_c, &fp_c, &ep_c, &wv_c};
+    for (int knob = 1; knob <= 4 && !rc; ++knob) {
+        for (int64_t val : *lists[knob]) {
+            if (val == cur[knob]) continue;
+            if (knob == 1 && val > 0 && static_cast<uint64_t>(kWave) * (val + 4) * 4 > static_cast<uint64_t>(c->lds_bytes)) continue;
+            int64_t o[5] = {cur[0], cur[1], cur[2], cur[3], cur[4]};
+            o[knob] = val;
+            apply(o);
+            double ms = 0;
+            if ((rc = trial_ms(&ms))) break;
+            if (ms < best) { best = ms; cur[knob] = val; }
+        }
+    }
+    if (!rc) {                              // the plain schedule as a whole
+        int64_t o[5] = {RASP_SCHED_PLAIN, cur[1], cur[2], cur[3], cur[4]};
+        apply(o);
+        double ms = 0;
+        rc = trial_ms(&ms);
+        if (!rc && ms < best) { best = ms; cur[0] = RASP_SCHED_PLAIN; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    release();
+    c->graph = saved[5];
+    c->profile = saved[6];
+    if (rc) {
+        const int64_t back[5] = {saved[0], saved[1], saved[2], saved[3], saved[4]};
+        apply(back);
+        return rc;
+    }
+    apply(cur);
+    if (chosen) for (int q = 0; q < 5; ++q) chosen[q] = cur[q];
+    if (best_ms) *best_ms = best;
     return RASP_OK;
 }
 

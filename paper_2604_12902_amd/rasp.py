@@ -37,7 +37,7 @@ EXPORTED = ("rasp_create", "rasp_destroy", "rasp_last_error", "rasp_batch_footpr
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
             "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
-            "rasp_kernel_times", "rasp_running_counts")
+            "rasp_kernel_times", "rasp_running_counts", "rasp_autotune")
 
 _ERRNAMES = {RASP_E_INVAL: "RASP_E_INVAL", RASP_E_NOMEM: "RASP_E_NOMEM",
              RASP_E_DEVICE: "RASP_E_DEVICE", RASP_E_STATE: "RASP_E_STATE",
@@ -92,6 +92,7 @@ def load_library(path: str = LIB_PATH):
         "rasp_device_info": ([P, P, P, P], i32),
         "rasp_kernel_times": ([P, P, P], i32),
         "rasp_running_counts": ([P, P, u32, P], i32),
+        "rasp_autotune": ([P, u64, u64, u64, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -266,6 +267,19 @@ def rasp_running_counts(ctx, batches) -> np.ndarray:
     hs = np.ascontiguousarray(batches, np.uint64)
     out = np.zeros(len(hs), np.uint64)
     _check(_lib.rasp_running_counts(ctx, _ptr(hs), len(hs), _ptr(out)), ctx)
+    return out
+
+
+AUTOTUNE_KNOBS = ("schedule", "lds_words", "first_pass", "epoch", "waves_per_cu")
+
+
+def rasp_autotune(ctx, batch: int, budget: int, max_vms: int = 0) -> dict:
+    """Pick and set the scheduling knobs for batches shaped like `batch`."""
+    chosen = np.zeros(5, np.int64)
+    best = ctypes.c_double()
+    _check(_lib.rasp_autotune(ctx, batch, budget, max_vms, _ptr(chosen), ctypes.byref(best)), ctx)
+    out = {k: int(v) for k, v in zip(AUTOTUNE_KNOBS, chosen)}
+    out["best_ms"] = best.value
     return out
 
 

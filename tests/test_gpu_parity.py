@@ -340,3 +340,53 @@ def test_lazy_descriptor_without_run_and_in_a_mix(ctx, rasp):
     compare(ctx.fetch(hc, mem=True), oracle.run(b2, 0))
     for x in (ha, hb, hc):
         ctx.free(x)
+
+
+@pytest.mark.parametrize("sched", ["plain", "firstpass-lds64"])
+def test_graph_replays_match_eager(ctx, rasp, sched):
+    """RASP_OPT_GRAPH: the captured launch sequence is replayed several times,
+    with eager work and synchronizations between replays; every replay's state
+    equals the oracle's state after the same total budget."""
+    configure(ctx, rasp, sched)
+    ctx.set(rasp.RASP_OPT_GRAPH, 1)
+    try:
+        b, other = W.config1(seed=71), W.tiny_random(seed=72, num_vms=2000)
+        h = ctx.load(b)
+        for rep in range(1, 5):
+            ctx.run(h, 70)                               # replay (captured on rep 1)
+            got = ctx.fetch(h, mem=True)                 # synchronizes
+            compare(got, oracle.run(b, 70 * rep))
+            ho = ctx.load(other)                         # eager work between replays
+            ctx.run(ho, 33 * rep)
+            compare(ctx.fetch(ho, mem=True), oracle.run(other, 33 * rep))
+            ctx.free(ho)
+        ctx.free(h)
+    finally:
+        ctx.set(rasp.RASP_OPT_GRAPH, 0)
+
+
+def test_autotune_leaves_the_batch_and_stays_bit_exact(ctx, rasp):
+    R = rasp
+    b = W.config3(num_vms=6000, seed=81, budget=2000)
+    h = ctx.load(b)
+    ctx.run(h, 100)
+    before = ctx.fetch(h, mem=True)
+    chosen = R.rasp_autotune(ctx.handle, h, 1900, max_vms=3000)
+    print("autotune chose", chosen, flush=True)
+    assert chosen["best_ms"] > 0
+    for k in R.AUTOTUNE_KNOBS:
+        assert ctx.get({"schedule": R.RASP_OPT_SCHEDULE, "lds_words": R.RASP_OPT_LDS_WORDS,
+                        "first_pass": R.RASP_OPT_FIRST_PASS, "epoch": R.RASP_OPT_EPOCH,
+                        "waves_per_cu": R.RASP_OPT_WAVES_PER_CU}[k]) == chosen[k]
+    after = ctx.fetch(h, mem=True)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    ctx.run(h, 1900)
+    compare(ctx.fetch(h, mem=True), oracle.run(b, 2000))
+    ctx.free(h)
+    # restore the defaults for the other tests
+    ctx.set(R.RASP_OPT_SCHEDULE, 0)
+    ctx.set(R.RASP_OPT_LDS_WORDS, -1)
+    ctx.set(R.RASP_OPT_FIRST_PASS, 64)
+    ctx.set(R.RASP_OPT_EPOCH, 256)
+    ctx.set(R.RASP_OPT_WAVES_PER_CU, 16)

@@ -19,6 +19,8 @@ Workloads (sizes of the stated populations):
   plain-small  4,096 x 16 instructions, n = 32, budget 256
   uneven       4,194,304 programs of 8..512 instructions, budget 65,536
   rollouts     262,144 counted-loop array programs, n = 2,048, budget 2^20
+  fig1         262,144 uniform Sec. 2.2 programs of 100 terminals, word RASP,
+               n = 250, l = 10, s = 2, budget 10^6 (the Sec. 3 evaluation)
 """
 from __future__ import annotations
 
@@ -42,9 +44,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain-scale",
-                    choices=["plain-scale", "plain-small", "uneven", "rollouts", "serve"])
-    ap.add_argument("--requests", type=int, default=120, help="serve: requests per run")
-    ap.add_argument("--loads", default="0.5,0.8", help="serve: offered load, fractions of capacity")
+                    choices=["plain-scale", "plain-small", "uneven", "rollouts", "fig1", "serve"])
+    ap.add_argument("--requests", type=int, default=500, help="serve: requests per run")
+    ap.add_argument("--loads", default="0.5,0.8,1.0", help="serve: offered load, fractions of capacity")
     ap.add_argument("--cap-gb", type=float, default=200.0, help="serve: arena footprint cap")
     ap.add_argument("--serve-epoch", type=int, default=4096, help="serve: transitions per epoch")
     ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
@@ -55,8 +57,13 @@ def parse():
     ap.add_argument("--lds-words", type=int, default=None)
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
-    ap.add_argument("--lazy", action="store_true",
-                    help="load with RASP_DESC_LAZY (c0 built inside the run)")
+    ap.add_argument("--eager", action="store_true",
+                    help="build c0 in rasp_load_batch instead of inside the run (RASP_DESC_LAZY)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default knobs instead of running rasp_autotune")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="bytes of one plain device-to-device copy run before the workload "
+                         "(the reference dispatch for HBM byte counters)")
     ap.add_argument("--json-extra", default="", help="path to write the full report")
     return ap.parse_args()
 
@@ -72,6 +79,8 @@ def make_batch(args):
         return W.config1(**kw)
     if args.workload == "uneven":
         return W.config3(**kw)
+    if args.workload == "fig1":
+        return W.fig1(workers=min(16, os.cpu_count() or 1), **kw)
     return W.config4(**kw)
 
 
@@ -162,6 +171,27 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def kernels_source_sha() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2604_12902_amd", "csrc", "rasp_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or
+    None when there is none or the kernels have changed since."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernels_sha256") != kernels_source_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -197,8 +227,9 @@ def main():
         cores, cpu_s, total_steps, bstep), flush=True)
 
     dev = torch.device("cuda", 0)
-    # inputs resident in HBM (with --lazy, c0 is built inside the run)
-    desc = R.make_desc(batch, dev, lazy=args.lazy)
+    # inputs resident in HBM; by default c0 is built inside the run (the first
+    # plain pass packs each wave's machines before stepping them)
+    desc = R.make_desc(batch, dev, lazy=not args.eager)
     N = batch.N
     outs = dict(status=torch.empty(N, dtype=torch.uint8, device=dev),
                 steps=torch.empty(N, dtype=torch.int64, device=dev),
@@ -207,12 +238,35 @@ def main():
                 u0=torch.empty(N, dtype=torch.int32, device=dev),
                 y0=torch.empty(N, dtype=torch.int32, device=dev),
                 y=torch.empty(int(batch.out_cap.astype(np.int64).sum()), dtype=torch.int32, device=dev))
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     fp = R.rasp_batch_footprint(desc)
-    arena = int(fp * 1.25) + (256 << 20)
+    tune_vms = min(N, 1 << 18)
+    # the batch, its autotune snapshot and trial copy of a prefix, and slack
+    arena = int(fp * (1.25 + 2.0 * tune_vms / N)) + (256 << 20)
     ctx = R.Context(arena)
     torch.cuda.synchronize()
 
+    tuned = None
+    if not args.no_autotune:
+        # the library's autotuner picks the knobs on a snapshot (untimed)
+        h = R.rasp_load_batch(ctx.handle, desc)
+        tuned = R.rasp_autotune(ctx.handle, h, budget, max_vms=tune_vms)
+        R.rasp_free_batch(ctx.handle, h)
+        print("bench: autotune chose %s" % tuned, flush=True)
+
     def configure(schedule):
+        if tuned is not None and schedule == R.RASP_SCHED_PERSISTENT:
+            ctx.set(R.RASP_OPT_LDS_WORDS, tuned["lds_words"])
+            ctx.set(R.RASP_OPT_FIRST_PASS, tuned["first_pass"])
+            ctx.set(R.RASP_OPT_EPOCH, tuned["epoch"])
+            ctx.set(R.RASP_OPT_WAVES_PER_CU, tuned["waves_per_cu"])
+            ctx.set(R.RASP_OPT_FIRST_PASS_KIND, tuned["first_pass_kind"])
         ctx.set(R.RASP_OPT_SCHEDULE, schedule)
         if args.first_pass is not None:
             ctx.set(R.RASP_OPT_FIRST_PASS, args.first_pass)
@@ -288,29 +342,37 @@ def main():
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
     dom_ms = kt[dom][0] / kt[dom][1]
     fp_pass = int(ctx.get(R.RASP_OPT_FIRST_PASS))
-    fused = kt["pack"][1] == 0 and kt["plain"][1] == 0
-    if fused:
+    # which launch built c0: the pack kernel, the first pass (plain or LDS
+    # persistent kernel) or the persistent kernel itself
+    first_kind = "first" if kt["first"][1] else ("plain" if kt["plain"][1] else None)
+    if first_kind is None:
         fp_pass = 0
-    steps_plain_pass = int(np.minimum(ref.steps.astype(np.int64), fp_pass).sum())
+    c0_in = "pack" if kt["pack"][1] else (first_kind or "persistent")
+    steps_first = int(np.minimum(ref.steps.astype(np.int64), fp_pass).sum())
+    c0_note = "c0 built in the launch (programs + inputs read, n+l+s words + 25 B scalars written per machine)"
     if dom == "pack":
         algo = pack_bytes(batch)
         unit_note = "c0 bytes: programs + inputs read, n+l+s words + 25 B scalars written per machine"
-    elif dom == "persistent" and fused:
+    elif dom == first_kind:
+        if c0_in == dom:
+            algo = pack_bytes(batch) + bstep * steps_first + 25.0 * N
+            unit_note = "%s + %.2f B per retired step + 25 B final state per machine" % (c0_note, bstep)
+        else:
+            algo = bstep * steps_first + 50.0 * N
+            unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
+    elif dom == "persistent" and c0_in == "persistent":
         algo = pack_bytes(batch) + bstep * total_steps + 25.0 * N
-        unit_note = ("c0 built in the launch (programs + inputs read, n+l+s words + 25 B scalars "
-                     "written per machine) + %.2f B per retired step + 25 B final state per machine" % bstep)
+        unit_note = "%s + %.2f B per retired step + 25 B final state per machine" % (c0_note, bstep)
     elif dom == "persistent":
-        algo = bstep * (total_steps - steps_plain_pass) + 50.0 * int((ref.steps > fp_pass).sum())
-        unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
-    elif dom == "plain":
-        algo = bstep * steps_plain_pass + 50.0 * N
+        algo = bstep * (total_steps - steps_first) + 50.0 * int((ref.steps > fp_pass).sum())
         unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
     else:
         algo = 0.0
         unit_note = "n/a"
     achieved = algo / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, dom)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
             "kernel": dom, "kernel_ms": round(dom_ms, 4), "algorithmic_bytes": int(algo),
             "per_unit": unit_note}
 
@@ -330,9 +392,10 @@ def main():
         "config": {"workload": batch.name, "num_vms": N, "budget": budget,
                    "retired_steps_per_batch": total_steps, "schedule": "persistent",
                    "first_pass": fp_pass, "lds_words": int(ctx.get(R.RASP_OPT_LDS_WORDS)),
-                   "c0_in_run": bool(fused),
+                   "c0_in_run": not args.eager, "autotuned": tuned is not None,
                    "epoch": int(ctx.get(R.RASP_OPT_EPOCH)),
-                   "waves_per_cu": int(ctx.get(R.RASP_OPT_WAVES_PER_CU))},
+                   "waves_per_cu": int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
+                   "first_pass_kind": int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND))},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "plain": ({k: results["plain"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms")}
                   if "plain" in results else None),

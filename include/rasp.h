@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define RASP_ABI_VERSION 1u
+#define RASP_ABI_VERSION 2u
 
 typedef struct rasp_ctx rasp_ctx;
 typedef uint64_t rasp_batch;                 /* 0 is never a valid handle */
@@ -123,6 +123,12 @@ const char *rasp_last_error(const rasp_ctx *ctx);
  * call that takes the descriptor returns (host) or until the work it queues
  * has finished on the context stream (device; with RASP_DESC_LAZY until the
  * batch's first run or fetch has finished).
+ * Word width (Sec. 2.1, W = F_2^w): word_bits w in [2, 32] (0 means 32).
+ * Every word of the machine is then a w-bit two's-complement value held
+ * sign-extended in an int32: ADD, SUB, MUL and the advance i + 2 (and the
+ * operand position i + 1) wrap mod 2^w.  Program and input words must already
+ * be w-bit values (RASP_E_INVAL otherwise); App. B's halting numbers are
+ * quoted at w = 29.
  */
 typedef struct {
     uint32_t abi_version;            /* RASP_ABI_VERSION */
@@ -138,7 +144,7 @@ typedef struct {
     const uint32_t *tape_cap;        /* NULL: l_v = |x_v| */
     const uint32_t *out_cap;         /* NULL: default_out_cap */
     uint32_t flags;                  /* RASP_DESC_* */
-    uint32_t reserved;
+    uint32_t word_bits;              /* w: 0 or 32 for 32-bit words, else 2..31 */
 } rasp_batch_desc;
 
 /*
@@ -189,7 +195,8 @@ int rasp_load_batch(rasp_ctx *ctx, const rasp_batch_desc *d, rasp_batch *out);
  * the isa; its program words are ignored beyond validation), then overwrite
  * every machine's i, a, u0, y0, steps, y and memory from `state` (host or
  * device per state->flags).  status is recomputed.  u0 <= l and y0 <= s are
- * required.  Used to resume from a checkpoint and to test arbitrary states.
+ * required, and with w < 32 every word (i, a, memory, output) must be a
+ * w-bit value.  Used to resume from a checkpoint and to test arbitrary states.
  * Errors: INVAL, NOMEM, DEVICE.
  */
 int rasp_load_state(rasp_ctx *ctx, const rasp_batch_desc *d, const rasp_outputs *state,
@@ -263,9 +270,14 @@ int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
  *                          budgets, knobs) and replay it as a HIP graph; graphs
  *                          of a batch are dropped when it is freed
  *   RASP_OPT_FIRST_PASS    persistent schedule only: transitions every machine
- *                          first runs in a plain one-machine-per-lane pass;
- *                          the machines still running then go through the
- *                          persistent kernel (0: persistent kernel only)
+ *                          first runs in a first pass; the machines still
+ *                          running then go through the persistent kernel
+ *                          (0: persistent kernel only)
+ *   RASP_OPT_FIRST_PASS_KIND  0: the first pass is the plain kernel (memory
+ *                          in HBM, one machine per lane); 1 (default): the
+ *                          persistent kernel with every machine's memory in
+ *                          its LDS slot, when every memory fits a slot
+ *                          (otherwise the plain kernel)
  */
 enum {
     RASP_OPT_SCHEDULE = 1,
@@ -273,7 +285,8 @@ enum {
     RASP_OPT_LDS_WORDS = 3,
     RASP_OPT_WAVES_PER_CU = 4,
     RASP_OPT_GRAPH = 5,
-    RASP_OPT_FIRST_PASS = 6
+    RASP_OPT_FIRST_PASS = 6,
+    RASP_OPT_FIRST_PASS_KIND = 8
 };
 enum { RASP_SCHED_AUTO = 0, RASP_SCHED_PLAIN = 1, RASP_SCHED_PERSISTENT = 2 };
 
@@ -293,7 +306,8 @@ enum {
     RASP_KERNEL_PERSISTENT = 2,    /* work-queue step loop                      */
     RASP_KERNEL_DIGEST = 3,        /* memory digests                            */
     RASP_KERNEL_OTHER = 4,         /* checks, scans, copies, queue reset        */
-    RASP_KERNEL_COUNT = 5
+    RASP_KERNEL_FIRST = 5,         /* work-queue first pass with LDS memory     */
+    RASP_KERNEL_COUNT = 6
 };
 enum { RASP_OPT_PROFILE = 7 };
 int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
@@ -303,10 +317,12 @@ int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
  * Copies the first min(num_vms, max_vms) machines of b into a scratch batch
  * (b itself is not changed), then times rasp_run(budget) on fresh copies of
  * that snapshot while searching one knob at a time (LDS words per machine,
- * first-pass length, epoch, waves per compute unit; persistent schedule
- * against plain), keeps the fastest setting in the context and writes it to
- * chosen[0..4] = {schedule, lds_words, first_pass, epoch, waves_per_cu}
- * (chosen may be NULL).  Returns the best time in *best_ms (may be NULL).
+ * first-pass length, epoch, waves per compute unit, first-pass kind;
+ * persistent schedule against plain), keeps the fastest setting in the
+ * context and writes it to chosen[0..5] = {schedule, lds_words, first_pass,
+ * epoch, waves_per_cu, first_pass_kind} (chosen may be NULL).  Returns the
+ * best time in *best_ms (may be NULL).  A lazily loaded batch stays lazy:
+ * each trial builds c0 of the prefix again from the descriptor.
  * Errors: STATE, NOMEM (no room for the snapshot), DEVICE.
  */
 int rasp_autotune(rasp_ctx *ctx, rasp_batch b, uint64_t budget, uint64_t max_vms,

@@ -8,8 +8,8 @@ stated directly).
 
 Two languages, both given as plain nested tuples:
 
-* the Sec. 2.2 array language: arrays ipt (declared length), opt (declared
-  output length) and scr (mu words), indexed modulo their length; + and * are
+* the Sec. 2.2 array language: arrays ipt (min(declared, l) words), opt
+  (min(declared, s) words) and scr (mu words), indexed modulo their length; + and * are
   word operations mod 2^w; ``ife G`` takes the first block when G is non-zero;
   ``whl G`` repeats while G is non-zero; ``hlt`` and the end of the body both
   print opt[0..l) and stop.
@@ -32,8 +32,12 @@ class OutOfFuel(Exception):
     pass
 
 
-def eval_paper(fun, w=32, ipt=None, mu=10, s=2, fuel=10 ** 7):
-    """Evaluate a Sec. 2.2 program; returns the printed words (at most s)."""
+def eval_paper(fun, w=32, ipt=None, mu=10, s=2, ell=10, fuel=10 ** 7):
+    """Evaluate a Sec. 2.2 program; returns the printed words (at most s).
+
+    The arrays have the sizes that the typing of Sec. 2.2 allows: ipt holds
+    min(declared, l) words and opt min(declared, s) words (ipt: W^(k <= l),
+    opt: W^(e <= s)); ``ipt`` gives the input words (missing ones are zero)."""
     _, n_in, n_out, body = fun
     mask = (1 << w) - 1
     sign = 1 << (w - 1)
@@ -42,8 +46,10 @@ def eval_paper(fun, w=32, ipt=None, mu=10, s=2, fuel=10 ** 7):
         v &= mask
         return v - (1 << w) if v & sign else v
 
-    arrs = {"ipt": [word(v) for v in (ipt or [0] * n_in)],
-            "opt": [0] * n_out, "scr": [0] * mu}
+    k_in, k_out = min(n_in, ell), min(n_out, s)
+    given = list(ipt or [])[:k_in]
+    arrs = {"ipt": [word(v) for v in given] + [0] * (k_in - len(given)),
+            "opt": [0] * k_out, "scr": [0] * mu}
     left = [fuel]
 
     def tick():
@@ -82,7 +88,7 @@ def eval_paper(fun, w=32, ipt=None, mu=10, s=2, fuel=10 ** 7):
         run(body)
     except _Halt:
         pass
-    return list(arrs["opt"])[:min(n_out, s)]
+    return list(arrs["opt"])
 
 
 def eval_counted(prog, tape, s):

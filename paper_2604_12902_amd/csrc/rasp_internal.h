@@ -10,6 +10,7 @@ namespace rasp {
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kMaxMulti = 64;          // batches per multi-batch launch
 constexpr uint32_t kMaxMemWords = 1u << 30;
+constexpr uint32_t kNoCap = 0xffffffffu;   // a persistent launch that is not a first pass
 
 // Device view of one batch: struct-of-arrays machine state plus the packed
 // per-machine shapes and the three word arenas (memory, tape, output), each
@@ -33,6 +34,8 @@ struct DevBatch {
     uint64_t N;
     uint32_t isa;
     uint32_t fresh;                    // 1: state is c0, built from the packed inputs below
+    uint32_t wshift;                   // 32 - w: words are w-bit values, sign-extended
+    uint32_t pad;
     const int32_t *prog;               // packed programs / inputs of a fresh batch
     const uint64_t *prog_off;
     const int32_t *tape;
@@ -64,7 +67,8 @@ enum : uint32_t {
     kErrProgTooLong = 2u,              // 2m > n
     kErrTapeTooLong = 4u,              // |x| > l
     kErrMemSize = 8u,                  // n == 0 or n > 2^30
-    kErrStateRange = 16u               // u0 > l or y0 > s in a loaded state
+    kErrStateRange = 16u,              // u0 > l or y0 > s in a loaded state
+    kErrWordRange = 32u                // a word outside the w-bit range
 };
 
 struct LaunchShape {
@@ -85,15 +89,31 @@ hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out_excl, uint64_t N,
 uint64_t scan_scratch_words(uint64_t N);
 hipError_t launch_pack(DevBatch b, const int32_t *prog, const uint64_t *prog_off,
                        const int32_t *tape, const uint64_t *tape_off, hipStream_t st);
-hipError_t launch_check_state(DevBatch b, uint32_t *err, hipStream_t st);
+hipError_t launch_check_state(DevBatch b, uint32_t *err, hipStream_t st);  // u0, y0, and i, a when w < 32
 hipError_t launch_probe(DevBatch b, hipStream_t st);
+// wm: some batch of the launch has words narrower than 32 bits
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap,
-                        uint32_t isa, bool pow2, uint32_t *surv, QueueState *q, hipStream_t st);
+                        uint32_t isa, bool pow2, bool pack, bool wm, uint32_t *surv, QueueState *q,
+                        hipStream_t st);
+// cap < UINT32_MAX with surv non-null: a first pass (machines still running
+// after cap transitions are appended to surv, q->survivors counts them)
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
-                             uint32_t already, uint32_t isa, bool pow2, uint32_t epoch, uint32_t lds_words,
-                             uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
+                             uint32_t already, uint32_t isa, bool pow2, bool wm, uint32_t epoch,
+                             uint32_t lds_words, uint32_t max_n, uint32_t max_ell,
+                             uint32_t waves_per_block, uint32_t blocks, uint32_t cap, uint32_t *surv,
                              QueueState *q, hipStream_t st);
+// err |= kErrWordRange if some of the `count` words is not a w-bit value
+hipError_t launch_check_words(const int32_t *w, uint64_t count, uint32_t wshift, uint32_t *err,
+                              hipStream_t st);
+// the same for words [off[0], off[N]) of w, the offsets in device memory
+hipError_t launch_check_words_off(const int32_t *w, const uint64_t *off, uint64_t N, uint32_t wshift,
+                                  uint32_t *err, hipStream_t st);
+// LDS words of one lane's slot for a launch (memory words, spare word and,
+// when every machine's memory fits, its tape); 0 for memory in HBM
+uint32_t slot_words(uint32_t lds_words, uint32_t max_n, uint32_t max_ell);
+constexpr uint32_t kTapeLdsMax = 64;     // tapes up to this many words are staged in LDS
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
+hipError_t launch_reset_head(QueueState *q, hipStream_t st);     // head = 0, counts kept
 void init_kernel_attributes();
 hipError_t launch_running(const BatchTable *tab, uint64_t total, unsigned long long *counts,
                           hipStream_t st);

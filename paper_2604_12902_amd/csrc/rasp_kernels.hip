@@ -14,7 +14,8 @@
 //   execute LOAD a <- j; ADD/SUB/MUL a <- a (+,-,*) M[j mod n]; STORE
 //           M[j mod n] <- a; READ M[j mod n] <- T[u0], u0++; PRINT (if y0 < s)
 //           Y[y0] <- M[j mod n], y0++; jumps i <- j; otherwise i <- i + 2;
-//           all word arithmetic wraps mod 2^32.
+//           all word arithmetic wraps mod 2^w (w = 32, or a narrower word
+//           held sign-extended in 32 bits).
 // `mod n` is the Euclidean remainder of the signed word (result in [0, n)).
 // The position p = i mod n is carried along with i so that the usual
 // sequential advance costs an add and a compare instead of a division.
@@ -37,22 +38,30 @@ __device__ __forceinline__ uint32_t cmod(int32_t v, uint32_t n)
     return static_cast<uint32_t>(r < 0 ? r + static_cast<int32_t>(n) : r);
 }
 
-// position of the operand word (i + 1) mod n, given p = i mod n
-__device__ __forceinline__ uint32_t operand_pos(int32_t i, uint32_t p, uint32_t n)
+// the w-bit word of x (ws = 32 - w): low w bits, sign-extended
+__device__ __forceinline__ int32_t sext(uint32_t x, uint32_t ws)
+{
+    return static_cast<int32_t>(x << ws) >> ws;
+}
+
+// position of the operand word (i + 1) mod n, given p = i mod n; imax is the
+// largest w-bit word, where i + 1 wraps to the smallest
+__device__ __forceinline__ uint32_t operand_pos(int32_t i, uint32_t p, uint32_t n, int32_t imax)
 {
     const uint32_t q = p + 1u;
     uint32_t r = q == n ? 0u : q;
-    if (i == INT32_MAX) r = cmod(INT32_MIN, n);             // i + 1 wraps
+    if (i == imax) r = cmod(-imax - 1, n);
     return r;
 }
 
-// position of i + 2 (wrapping) given p = i mod n
-__device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t n)
+// position of i + 2 (wrapping mod 2^w) given p = i mod n
+__device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t n, int32_t imax,
+                                                uint32_t ws)
 {
     uint32_t q = p + 2u;
     if (q >= n) q -= n;
     if (q >= n) q -= n;                                     // n == 1
-    if (i > INT32_MAX - 2) q = cmod(static_cast<int32_t>(static_cast<uint32_t>(i) + 2u), n);
+    if (i > imax - 2) q = cmod(sext(static_cast<uint32_t>(i) + 2u, ws), n);
     return q;
 }
 
@@ -65,9 +74,15 @@ __device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t 
 
 extern __shared__ int32_t rasp_lds[];
 
+// pointers known to address global memory: loads and stores compile to
+// global_* instructions instead of flat_* ones (which also wait on LDS)
+typedef __attribute__((address_space(1))) int32_t gi32;
+__device__ __forceinline__ gi32 *gptr(int32_t *p) { return (gi32 *)p; }
+__device__ __forceinline__ const gi32 *gptr(const int32_t *p) { return (const gi32 *)p; }
+
 struct GlobalMem {                       // every word in HBM
     static constexpr bool kLds = false;
-    int32_t *M;
+    gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
     __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
     {
@@ -93,7 +108,7 @@ struct LdsMem {                          // whole memory in the lane's LDS slot 
 struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     static constexpr bool kLds = false;
     uint32_t base, P;
-    int32_t *M;
+    gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const
     {
         int32_t v;
@@ -110,6 +125,19 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     {
         if (en) { if (k < P) rasp_lds[base + k] = v; else M[k] = v; }
     }
+};
+
+// input tape: in HBM, or staged in the lane's LDS slot
+struct TapeG {
+    static constexpr bool kLds = false;
+    const gi32 *T;
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return T[k]; }
+};
+
+struct TapeL {
+    static constexpr bool kLds = true;
+    uint32_t base;
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -136,19 +164,37 @@ struct Regs {
 // division and no special case.  Otherwise the common case -- operand word in
 // [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code and
 // everything else takes one branch that lanes skip when none needs it.
-template <int ISA, bool POW2, class Mem>
-__device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
-                                                const int32_t *__restrict__ T,
-                                                int32_t *__restrict__ Y,
-                                                uint32_t limit, bool &halted, bool &wrote)
+// the fixed-point predicate of the current configuration (F of Sec. 1.1/2.1):
+// unknown opcode, READ with the tape used up, or a taken jump onto itself
+template <int ISA>
+__device__ __forceinline__ bool stuck(uint32_t op, int32_t j, int32_t a, int32_t i, uint32_t u0, uint32_t ell)
+{
+    bool taken, valid;
+    if (ISA == 1) {
+        taken = (op == 8u) | ((op == 5u) & (a > 0));
+        valid = (op - 1u) < 8u;
+    } else {
+        taken = (op == 5u) & (a != 0);
+        valid = (op - 1u) < 7u;
+    }
+    return !valid | ((op == 6u) & (u0 >= ell)) | (taken & (j == i));
+}
+
+// WM: words narrower than 32 bits (ws = 32 - w; POW2 then also needs n <= 2^w)
+template <int ISA, bool POW2, bool WM, class Mem, class Tape>
+__device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape, Regs &r,
+                                                gi32 *__restrict__ Y,
+                                                uint32_t limit, bool &halted, bool &wrote,
+                                                uint32_t ws)
 {
     const uint32_t n = r.n, nm = r.n - 1u, ell = r.ell, s = r.s;
+    const int32_t imax = WM ? static_cast<int32_t>(0x7fffffffu >> ws) : INT32_MAX;
     uint32_t p = r.p, u0 = r.u0, y0 = r.y0;
     int32_t i = r.i, a = r.a;
     int32_t o = mem.ld(p);
-    int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n));
+    int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
     uint32_t left = limit;
-    bool wr = false, fixed;
+    uint32_t wr = 0;
     for (;;) {
         const uint32_t op = static_cast<uint32_t>(o);
         const bool is_rd = op == 6u;
@@ -161,12 +207,13 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
             valid = (op - 1u) < 7u;
         }
         const bool rd_ok = is_rd & (u0 < ell);
-        fixed = !valid | (is_rd & !rd_ok) | (taken & (j == i));
+        const bool fixed = !valid | (is_rd & !rd_ok) | (taken & (j == i));
         if (fixed | (left == 0u)) break;
 
         // positions: data word jj = j mod n, next instruction np, its operand nq
         uint32_t jj, seq, np, nq;
-        const int32_t ni = taken ? j : static_cast<int32_t>(static_cast<uint32_t>(i) + 2u);
+        const uint32_t i2 = static_cast<uint32_t>(i) + 2u;
+        const int32_t ni = taken ? j : (WM ? sext(i2, ws) : static_cast<int32_t>(i2));
         if (POW2) {
             jj = static_cast<uint32_t>(j) & nm;
             seq = (p + 2u) & nm;
@@ -176,22 +223,30 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
             jj = static_cast<uint32_t>(j);
             seq = p + 2u;
             seq = seq >= n ? seq - n : seq;
-            const bool rare = (static_cast<uint32_t>(j) >= n) | (i >= INT32_MAX - 3) | (n < 2u);
+            // with w < 32 a jump target j < n can also be the largest word,
+            // whose operand position i + 1 wraps
+            bool rare = (static_cast<uint32_t>(j) >= n) | (i >= imax - 3) | (n < 2u);
+            if (WM) rare |= j >= imax - 3;
             if (rare) {
                 jj = cmod(j, n);
-                seq = advance_pos(i, p, n);
+                seq = advance_pos(i, p, n, imax, WM ? ws : 0u);
             }
             np = taken ? jj : seq;
             nq = np + 1u;
             nq = nq == n ? 0u : nq;
-            if (rare) nq = operand_pos(ni, np, n);
+            if (rare) nq = operand_pos(ni, np, n, imax);
         }
 
         const bool st_en = (op == 4u) | rd_ok;
         int32_t w = a;
-        if (rd_ok) w = T[u0];
+        if (Tape::kLds) {
+            const int32_t tv = tape.ld(u0 < ell ? u0 : 0u);    // staged: read unconditionally
+            w = rd_ok ? tv : a;
+        } else if (rd_ok) {
+            w = tape.ld(u0);
+        }
         mem.st(jj, w, st_en);
-        wr |= st_en;
+        wr |= st_en ? 1u : 0u;
         u0 += rd_ok ? 1u : 0u;
         const bool need = (op == 2u) | (op == 3u) | (op == 7u);
         const int32_t d = mem.ld_data(jj, need);
@@ -202,6 +257,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
         const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);
         uint32_t na = op == 3u ? (ISA == 1 ? ua - ud : ua * ud) : ua;
         na = op == 2u ? ua + ud : na;
+        if (WM) na = static_cast<uint32_t>(sext(na, ws));
         na = op == 1u ? static_cast<uint32_t>(jcur) : na;
         a = static_cast<int32_t>(na);
         const bool app = (op == 7u) & (y0 < s);
@@ -211,8 +267,8 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, Regs &r,
         p = np;
         --left;
     }
-    halted = fixed;
-    wrote |= wr;
+    halted = stuck<ISA>(static_cast<uint32_t>(o), j, a, i, u0, ell);
+    wrote |= wr != 0u;
     r.i = i; r.a = a; r.p = p; r.u0 = u0; r.y0 = y0;
     return limit - left;
 }
@@ -314,9 +370,10 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     r.n = b.n[v]; r.ell = b.ell[v]; r.s = b.s[v];
     r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
     r.p = cmod(r.i, r.n);
-    GlobalMem g{b.M + b.mem_off[v]};
+    GlobalMem g{gptr(b.M + b.mem_off[v])};
+    TapeG tg{gptr(b.T + b.t_off[v])};
     bool halted, wrote = false;
-    run_machine<ISA, false>(g, r, b.T + b.t_off[v], b.Y + b.y_off[v], 0u, halted, wrote);
+    run_machine<ISA, false, true>(g, tg, r, gptr(b.Y + b.y_off[v]), 0u, halted, wrote, b.wshift);
     b.status[v] = halted ? 1 : 0;
 }
 
@@ -335,41 +392,103 @@ hipError_t launch_probe(DevBatch b, hipStream_t st)
 // atomic) to the survivor list for the persistent kernel.
 // ---------------------------------------------------------------------------
 
-template <int ISA, bool POW2>
+template <int ISA, bool POW2, bool PACK>
 __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ tab, uint64_t total,
-                                               uint32_t cap, uint32_t *__restrict__ surv,
+                                               uint32_t cap, uint32_t wm, uint32_t *__restrict__ surv,
                                                QueueState *__restrict__ q)
 {
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
     bool survive = false;
+    int k = 0;
+    uint64_t v = 0;
     if (g < total) {
-        const int k = batch_of(tab, g);
-        const DevBatch &b = tab->b[k];
-        const uint64_t v = g - tab->start[k];
+        k = batch_of(tab, g);
+        v = g - tab->start[k];
+    }
+    const DevBatch &b = tab->b[k];
+    const bool fresh = PACK && g < total && b.fresh;
+    if (PACK) {
+        // build c0 (Sec. 2.1) of this wave's fresh machines first: each
+        // machine's memory slice written by the whole wave, 16 bytes a lane
+        uint64_t p0 = 0, t0 = 0;
+        uint32_t plen = 0, tlen = 0, n = 0, ell = 0, s = 0;
+        const int32_t *src = nullptr, *tsrc = nullptr;
+        int32_t *Md = nullptr, *Td = nullptr, *Yd = nullptr;
+        if (fresh) {
+            p0 = b.prog_off[v];
+            plen = static_cast<uint32_t>(b.prog_off[v + 1] - p0);
+            t0 = b.tape_off[v];
+            tlen = static_cast<uint32_t>(b.tape_off[v + 1] - t0);
+            n = b.n[v]; ell = b.ell[v]; s = b.s[v];
+            src = b.prog + p0; tsrc = b.tape + t0;
+            Md = b.M + b.mem_off[v]; Td = b.T + b.t_off[v]; Yd = b.Y + b.y_off[v];
+        }
+        uint64_t fm = __ballot(fresh);
+        while (fm) {
+            const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
+            fm &= fm - 1;
+            const int32_t *S = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(src), L));
+            int32_t *D = reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Md), L));
+            const uint32_t PL = bcast(plen, L), NN = bcast(n, L);
+            const bool al = (bcast64(p0, L) & 3u) == 0;
+            for (uint32_t kk = 4 * lane; kk < NN; kk += 4 * kWave) {
+                int4 w;
+                if (al && kk + 4 <= PL) {
+                    w = *reinterpret_cast<const int4 *>(S + kk);
+                } else {
+                    w.x = kk < PL ? S[kk] : 0;
+                    w.y = kk + 1 < PL ? S[kk + 1] : 0;
+                    w.z = kk + 2 < PL ? S[kk + 2] : 0;
+                    w.w = kk + 3 < PL ? S[kk + 3] : 0;
+                }
+                *reinterpret_cast<int4 *>(D + kk) = w;
+            }
+            const int32_t *TS = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L));
+            int32_t *TD = reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Td), L));
+            int32_t *YD = reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Yd), L));
+            const uint32_t TL = bcast(tlen, L), EL = bcast(ell, L), SS = bcast(s, L);
+            for (uint32_t e = lane; e < EL; e += kWave) TD[e] = e < TL ? TS[e] : 0;
+            for (uint32_t e = lane; e < SS; e += kWave) YD[e] = 0;
+        }
+        // the wave's own stores must be visible to its lanes' loads below
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (g < total) {
         const uint32_t budget = tab->budget[k];
-        if (b.status[v] == 0 && budget > 0) {
+        if ((fresh || b.status[v] == 0) && budget > 0) {
             Regs r;
             r.n = b.n[v]; r.ell = b.ell[v]; r.s = b.s[v];
-            r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
+            if (fresh) {
+                r.i = 0; r.a = 0; r.u0 = 0; r.y0 = 0;
+            } else {
+                r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
+            }
             r.p = cmod(r.i, r.n);
             const uint32_t limit = cap < budget ? cap : budget;
-            GlobalMem m{b.M + b.mem_off[v]};
+            GlobalMem m{gptr(b.M + b.mem_off[v])};
+            TapeG tg{gptr(b.T + b.t_off[v])};
             bool halted, wrote = false;
-            const uint32_t t = run_machine<ISA, POW2>(m, r, b.T + b.t_off[v], b.Y + b.y_off[v], limit,
-                                                      halted, wrote);
-            if (t) {
+            const uint32_t t = wm ? run_machine<ISA, POW2, true>(m, tg, r, gptr(b.Y + b.y_off[v]), limit,
+                                                                 halted, wrote, b.wshift)
+                                  : run_machine<ISA, POW2, false>(m, tg, r, gptr(b.Y + b.y_off[v]), limit,
+                                                                  halted, wrote, 0u);
+            if (t || fresh) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
-                b.steps[v] += t;
+                b.steps[v] = fresh ? t : b.steps[v] + t;
             }
-            if (halted) b.status[v] = 1;
+            if (halted || fresh) b.status[v] = halted ? 1 : 0;
             survive = !halted && t == limit && limit < budget;
+        } else if (fresh) {
+            // budget 0: c0 only
+            b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0; b.status[v] = 0;
         }
     }
     if (surv != nullptr) {
         const uint64_t mask = __ballot(survive);
         if (mask) {
             const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-            const uint32_t lane = threadIdx.x & (kWave - 1);
             unsigned long long base = 0;
             if (lane == static_cast<uint32_t>(leader))
                 base = atomicAdd(&q->survivors, static_cast<unsigned long long>(__popcll(mask)));
@@ -382,16 +501,25 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
     }
 }
 
+template <int ISA, bool POW2>
+static void plain_go(bool pack, unsigned blocks, hipStream_t st, const BatchTable *tab, uint64_t total,
+                     uint32_t cap, uint32_t wm, uint32_t *surv, QueueState *q)
+{
+    if (pack) k_plain<ISA, POW2, true><<<blocks, 256, 0, st>>>(tab, total, cap, wm, surv, q);
+    else k_plain<ISA, POW2, false><<<blocks, 256, 0, st>>>(tab, total, cap, wm, surv, q);
+}
+
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uint32_t isa,
-                        bool pow2, uint32_t *surv, QueueState *q, hipStream_t st)
+                        bool pow2, bool pack, bool wm, uint32_t *surv, QueueState *q, hipStream_t st)
 {
     const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
+    const uint32_t w = wm ? 1u : 0u;
     if (isa == 1) {
-        if (pow2) k_plain<1, true><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
-        else k_plain<1, false><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+        if (pow2) plain_go<1, true>(pack, blocks, st, tab, total, cap, w, surv, q);
+        else plain_go<1, false>(pack, blocks, st, tab, total, cap, w, surv, q);
     } else {
-        if (pow2) k_plain<0, true><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
-        else k_plain<0, false><<<blocks, 256, 0, st>>>(tab, total, cap, surv, q);
+        if (pow2) plain_go<0, true>(pack, blocks, st, tab, total, cap, w, surv, q);
+        else plain_go<0, false>(pack, blocks, st, tab, total, cap, w, surv, q);
     }
     return hipGetLastError();
 }
@@ -404,32 +532,60 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uin
 // ballot + popcount prefix ranks).
 // MODE 0: memory in HBM.  MODE 1: each live machine's whole memory is staged
 // in its lane's LDS slot of P words (every n <= P).  MODE 2: words [0, P) in
-// LDS, the rest in HBM.  Staging and write-back are cooperative 16-byte
-// copies by the whole wave; only machines that stored into LDS are written
-// back.  Work item k is machine work[k] of the launch (or machine k when work
-// is null); machines have already applied `already` transitions this run.
+// LDS, the rest in HBM.  Staging and write-back are cooperative: the whole
+// wave moves one machine's words at a time, 16 bytes a lane (1 KB per
+// instruction, coalesced), with four machines' loads in flight before their
+// writes; only machines that stored into LDS (or are new) are written back.
+// Work item k is machine work[k] of the launch (or machine k when work is
+// null); machines have already applied `already` transitions this run.
+// With surv non-null the launch is a first pass: a machine runs at most `cap`
+// transitions, and one still running after them is written back and appended
+// to surv (its index in the launch) for a later launch.
 // ---------------------------------------------------------------------------
 
-template <int ISA, int MODE, bool POW2>
+// four words as one 16-byte access; global and LDS views of it
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4i gv4i;
+
+// 16 bytes of global memory at word k of S (S 16-byte aligned when al), with
+// words at or beyond len read as zero
+__device__ __forceinline__ v4i load4(const int32_t *S, uint32_t k, uint32_t len, bool al)
+{
+    const gi32 *G = gptr(S);
+    v4i w;
+    if (al && k + 4u <= len) {
+        w = *reinterpret_cast<const gv4i *>(G + k);
+    } else {
+        w.x = k < len ? G[k] : 0;
+        w.y = k + 1u < len ? G[k + 1u] : 0;
+        w.z = k + 2u < len ? G[k + 2u] : 0;
+        w.w = k + 3u < len ? G[k + 3u] : 0;
+    }
+    return w;
+}
+
+template <int ISA, int MODE, bool POW2, bool TLDS>
 __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict__ tab,
                                                     uint64_t total,
                                                     const uint32_t *__restrict__ work,
                                                     uint32_t already, uint32_t epoch,
-                                                    uint32_t P, QueueState *__restrict__ q)
+                                                    uint32_t P, uint32_t TL, uint32_t wm,
+                                                    uint32_t cap, uint32_t *__restrict__ surv,
+                                                    QueueState *__restrict__ q)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = threadIdx.x / kWave;
-    const uint32_t SP = P + 4u;                            // slot stride: P words + spare
+    const uint32_t SP = P + 4u + (TLDS ? TL : 0u);         // slot: P words, spare, tape
     const uint32_t wave_base = wib * kWave * SP;           // word index of lane 0's slot
     const uint32_t slot = wave_base + lane * SP;
-    if (work != nullptr) total = q->survivors;             // written by the plain pass
+    if (work != nullptr) total = q->survivors;             // written by the first pass
 
-    bool has = false, exhausted = false, wrote = false, fresh = false;
+    bool has = false, exhausted = false, wrote = false, fresh = false, cut = false;
     Regs r{};
     int32_t *M = nullptr;
-    const int32_t *T = nullptr;
+    int32_t *T = nullptr;
     int32_t *Y = nullptr;
-    uint32_t done = 0, limit = 0;
+    uint32_t done = 0, limit = 0, ws = 0, gid = 0;
     const DevBatch *bp = nullptr;
     uint64_t v = 0;
 
@@ -463,11 +619,15 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                             r.i = bp->i[v]; r.a = bp->a[v]; r.u0 = bp->u0[v]; r.y0 = bp->y0[v];
                         }
                         r.p = cmod(r.i, r.n);
+                        ws = bp->wshift;
                         M = bp->M + bp->mem_off[v];
                         T = bp->T + bp->t_off[v];
                         Y = bp->Y + bp->y_off[v];
+                        gid = static_cast<uint32_t>(g);
                         done = 0;
                         limit = budget - already;
+                        cut = cap < limit;
+                        if (cut) limit = cap;
                         wrote = false;
                         has = true;
                         claimed = true;
@@ -479,74 +639,114 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             if (exhausted) break;
             continue;
         }
-        // ---- stage the claimed machine's low memory words into the lane's slot ----
-        if (MODE != 0 && claimed) {
-            const uint32_t cnt = r.n < P ? r.n : P;
-            if (fresh) {
-                // c0 (Sec. 2.1): program words, zeros; tape x 0^(l-|x|); output 0^s
-                const uint64_t p0 = bp->prog_off[v];
-                const uint32_t plen = static_cast<uint32_t>(bp->prog_off[v + 1] - p0);
-                const int32_t *src = bp->prog + p0;
-                const bool al = (p0 & 3u) == 0;
-                // groups of 8 x 16 bytes: every load of a group is issued before its stores
-                for (uint32_t k0 = 0; k0 < cnt; k0 += 32) {
-                    int4 w[8];
+        // ---- stage the claimed machines' low memory words into their slots ----
+        if (MODE != 0) {
+            // what each claiming lane's copy reads: the packed program (c0 of a
+            // new machine, Sec. 2.1: program words, then zeros) or its memory
+            const int32_t *src = nullptr, *tsrc = nullptr;
+            uint32_t srclen = 0, cnt = 0, tlen = 0, al = 1;
+            if (claimed) {
+                cnt = r.n < P ? r.n : P;
+                if (fresh) {
+                    const uint64_t p0 = bp->prog_off[v], t0 = bp->tape_off[v];
+                    src = bp->prog + p0;
+                    srclen = static_cast<uint32_t>(bp->prog_off[v + 1] - p0);
+                    al = (p0 & 3u) == 0 ? 1u : 0u;
+                    tsrc = bp->tape + t0;
+                    tlen = static_cast<uint32_t>(bp->tape_off[v + 1] - t0);
+                } else {
+                    src = M;                                // 16-byte aligned, padded to 4 words
+                    srclen = (cnt + 3u) & ~3u;
+                    tsrc = T;
+                    tlen = r.ell;
+                }
+            }
+            const uint32_t fr = (claimed && fresh) ? 1u : 0u;
+            uint64_t cm = __ballot(claimed);
+            while (cm) {
+                uint32_t Ls[4], C[4], SL[4], D[4], AL[4], nL = 0, Cmax = 0;
+                const int32_t *S[4];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const uint32_t k = k0 + 4u * u;
-                        if (al && k + 4 <= plen) {
-                            w[u] = *reinterpret_cast<const int4 *>(src + k);
-                        } else {
-                            w[u].x = k < plen ? src[k] : 0;
-                            w[u].y = k + 1 < plen ? src[k + 1] : 0;
-                            w[u].z = k + 2 < plen ? src[k + 2] : 0;
-                            w[u].w = k + 3 < plen ? src[k + 3] : 0;
-                        }
+                for (int u = 0; u < 4; ++u) {
+                    C[u] = 0; SL[u] = 0; D[u] = 0; AL[u] = 1; S[u] = nullptr; Ls[u] = 0;
+                    if (cm) {
+                        const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
+                        cm &= cm - 1ull;
+                        Ls[u] = L;
+                        C[u] = bcast(cnt, L);
+                        SL[u] = bcast(srclen, L);
+                        AL[u] = bcast(al, L);
+                        S[u] = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(src), L));
+                        D[u] = wave_base + L * SP;
+                        Cmax = C[u] > Cmax ? C[u] : Cmax;
+                        nL = u + 1;
                     }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (k0 + 4u * u < cnt) *reinterpret_cast<int4 *>(&rasp_lds[slot + k0 + 4u * u]) = w[u];
                 }
-                const uint64_t t0 = bp->tape_off[v];
-                const uint32_t tlen = static_cast<uint32_t>(bp->tape_off[v + 1] - t0);
-                int32_t *Tw = const_cast<int32_t *>(T);
-                for (uint32_t e0 = 0; e0 < r.ell; e0 += 8) {
-                    int32_t x[8];
+                for (uint32_t k0 = 0; k0 < Cmax; k0 += 4u * kWave) {
+                    const uint32_t k = k0 + 4u * lane;
+                    v4i w[4];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) x[u] = e0 + u < tlen ? bp->tape[t0 + e0 + u] : 0;
+                    for (int u = 0; u < 4; ++u)
+                        if (k < C[u]) w[u] = load4(S[u], k, SL[u], AL[u] != 0);
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) if (e0 + u < r.ell) Tw[e0 + u] = x[u];
+                    for (int u = 0; u < 4; ++u)
+                        if (k < C[u]) *reinterpret_cast<v4i *>(&rasp_lds[D[u] + k]) = w[u];
                 }
-                for (uint32_t e = 0; e < r.s; ++e) Y[e] = 0;
-            } else {
-                for (uint32_t k0 = 0; k0 < cnt; k0 += 32) {
-                    int4 w[8];
+                // a new machine's tape x 0^(l-|x|) and output 0^s in HBM; the
+                // tape also into the slot when it is staged there
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (k0 + 4u * u < cnt) w[u] = *reinterpret_cast<const int4 *>(M + k0 + 4u * u);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        if (k0 + 4u * u < cnt) *reinterpret_cast<int4 *>(&rasp_lds[slot + k0 + 4u * u]) = w[u];
+                for (int u = 0; u < 4; ++u) {
+                    if (static_cast<uint32_t>(u) >= nL) break;
+                    const uint32_t L = Ls[u];
+                    const bool F = bcast(fr, L) != 0;
+                    if (!F && !TLDS) continue;
+                    const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L);
+                    const gi32 *TS = gptr(reinterpret_cast<const int32_t *>(
+                        bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
+                    gi32 *TD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(T), L)));
+                    for (uint32_t e = lane; e < EL; e += kWave) {
+                        const int32_t x = e < TN ? TS[e] : 0;
+                        if (F) TD[e] = x;
+                        if (TLDS) rasp_lds[D[u] + P + 4u + e] = x;
+                    }
+                    if (F) {
+                        const uint32_t SS = bcast(r.s, L);
+                        gi32 *YD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Y), L)));
+                        for (uint32_t e = lane; e < SS; e += kWave) YD[e] = 0;
+                    }
                 }
             }
         }
         // ---- run ----
-        bool finish = false;
+        bool finish = false, survive = false;
         if (has) {
             uint32_t lim = limit - done;
             if (lim > epoch) lim = epoch;
             bool halted;
             uint32_t t;
+            // wm is uniform: one of the two loop bodies runs
+#define RASP_RUN(mm, tp)                                                                        \
+    (wm ? run_machine<ISA, POW2, true>(mm, tp, r, gptr(Y), lim, halted, wrote, ws)             \
+        : run_machine<ISA, POW2, false>(mm, tp, r, gptr(Y), lim, halted, wrote, 0u))
             if (MODE == 1) {
                 LdsMem mm{slot, slot + P};
-                t = run_machine<ISA, POW2>(mm, r, T, Y, lim, halted, wrote);
+                if (TLDS) {
+                    TapeL tl{slot + P + 4u};
+                    t = RASP_RUN(mm, tl);
+                } else {
+                    TapeG tg{gptr(T)};
+                    t = RASP_RUN(mm, tg);
+                }
             } else if (MODE == 2) {
-                SplitMem mm{slot, P, M};
-                t = run_machine<ISA, POW2>(mm, r, T, Y, lim, halted, wrote);
+                SplitMem mm{slot, P, gptr(M)};
+                TapeG tg{gptr(T)};
+                t = RASP_RUN(mm, tg);
             } else {
-                GlobalMem mm{M};
-                t = run_machine<ISA, POW2>(mm, r, T, Y, lim, halted, wrote);
+                GlobalMem mm{gptr(M)};
+                TapeG tg{gptr(T)};
+                t = RASP_RUN(mm, tg);
             }
+#undef RASP_RUN
             done += t;
             if (halted || done == limit) {
                 if (done || fresh) {
@@ -555,38 +755,53 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                 }
                 if (halted || fresh) bp->status[v] = halted ? 1 : 0;
                 finish = true;
+                survive = cut && !halted;
             }
         }
-        // ---- write back the slot of a finished machine that stored (or is new) ----
-        if (MODE != 0 && finish && (wrote || fresh)) {
+        // ---- write back the slots of finished machines that stored (or are new) ----
+        if (MODE != 0) {
             const uint32_t cnt = r.n < P ? r.n : P;
-            for (uint32_t k0 = 0; k0 < cnt; k0 += 32) {
-                int4 w[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (k0 + 4u * u < cnt) w[u] = *reinterpret_cast<const int4 *>(&rasp_lds[slot + k0 + 4u * u]);
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (k0 + 4u * u < cnt) *reinterpret_cast<int4 *>(M + k0 + 4u * u) = w[u];
+            uint64_t fm = __ballot(finish && (wrote || fresh));
+            while (fm) {
+                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
+                fm &= fm - 1ull;
+                const uint32_t C = bcast(cnt, L), D = wave_base + L * SP;
+                gi32 *MD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L)));
+                for (uint32_t k = 4u * lane; k < C; k += 4u * kWave)
+                    *reinterpret_cast<gv4i *>(MD + k) = *reinterpret_cast<const v4i *>(&rasp_lds[D + k]);
+            }
+        }
+        // ---- first pass: append the machines still running to the survivor list ----
+        if (surv != nullptr) {
+            const uint64_t sm = __ballot(survive);
+            if (sm) {
+                const int leader = __ffsll(static_cast<unsigned long long>(sm)) - 1;
+                unsigned long long base = 0;
+                if (lane == static_cast<uint32_t>(leader))
+                    base = atomicAdd(&q->survivors, static_cast<unsigned long long>(__popcll(sm)));
+                base = __shfl(base, leader);
+                if (survive) surv[base + __popcll(sm & ((1ull << lane) - 1ull))] = gid;
             }
         }
         if (finish) has = false;
     }
 }
 
-template <int ISA, int MODE, bool POW2>
+template <int ISA, int MODE, bool POW2, bool TLDS>
 static hipError_t launch_k3(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const BatchTable *tab,
                             uint64_t total, const uint32_t *work, uint32_t already, uint32_t epoch,
-                            uint32_t P, QueueState *q)
+                            uint32_t P, uint32_t TL, uint32_t wm, uint32_t cap, uint32_t *surv,
+                            QueueState *q)
 {
-    k_persistent<ISA, MODE, POW2><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, P, q);
+    k_persistent<ISA, MODE, POW2, TLDS><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, P, TL,
+                                                                    wm, cap, surv, q);
     return hipGetLastError();
 }
 
-template <int ISA, int MODE, bool POW2>
+template <int ISA, int MODE, bool POW2, bool TLDS>
 static void lds_attr()
 {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<ISA, MODE, POW2>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent<ISA, MODE, POW2, TLDS>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
@@ -594,47 +809,74 @@ static void lds_attr()
 // per context, outside any stream capture.
 void init_kernel_attributes()
 {
-    lds_attr<0, 1, false>(); lds_attr<0, 1, true>(); lds_attr<0, 2, false>(); lds_attr<0, 2, true>();
-    lds_attr<1, 1, false>(); lds_attr<1, 1, true>(); lds_attr<1, 2, false>(); lds_attr<1, 2, true>();
+    lds_attr<0, 1, false, false>(); lds_attr<0, 1, true, false>();
+    lds_attr<0, 1, false, true>(); lds_attr<0, 1, true, true>();
+    lds_attr<0, 2, false, false>(); lds_attr<0, 2, true, false>();
+    lds_attr<1, 1, false, false>(); lds_attr<1, 1, true, false>();
+    lds_attr<1, 1, false, true>(); lds_attr<1, 1, true, true>();
+    lds_attr<1, 2, false, false>(); lds_attr<1, 2, true, false>();
     (void)hipGetLastError();
 }
 
-template <int ISA, int MODE>
+template <int ISA, int MODE, bool TLDS>
 static hipError_t launch_k3_p(bool pow2, dim3 grid, dim3 block, size_t shmem, hipStream_t st,
                               const BatchTable *tab, uint64_t total, const uint32_t *work,
-                              uint32_t already, uint32_t epoch, uint32_t P, QueueState *q)
+                              uint32_t already, uint32_t epoch, uint32_t P, uint32_t TL, uint32_t wm,
+                              uint32_t cap, uint32_t *surv, QueueState *q)
 {
-    return pow2 ? launch_k3<ISA, MODE, true>(grid, block, shmem, st, tab, total, work, already, epoch, P, q)
-                : launch_k3<ISA, MODE, false>(grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+    return pow2 ? launch_k3<ISA, MODE, true, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q)
+                : launch_k3<ISA, MODE, false, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+}
+
+uint32_t slot_words(uint32_t lds_words, uint32_t max_n, uint32_t max_ell)
+{
+    if (lds_words == 0) return 0;
+    const uint32_t tl = (max_n <= lds_words && max_ell <= kTapeLdsMax) ? ((max_ell + 3u) & ~3u) : 0u;
+    return lds_words + 4u + tl;
 }
 
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
-                             uint32_t already, uint32_t isa, bool pow2, uint32_t epoch, uint32_t lds_words,
-                             uint32_t max_n, uint32_t waves_per_block, uint32_t blocks,
+                             uint32_t already, uint32_t isa, bool pow2, bool wmb, uint32_t epoch,
+                             uint32_t lds_words, uint32_t max_n, uint32_t max_ell,
+                             uint32_t waves_per_block, uint32_t blocks, uint32_t cap, uint32_t *surv,
                              QueueState *q, hipStream_t st)
 {
+    const uint32_t wm = wmb ? 1u : 0u;
     const dim3 grid(blocks), block(waves_per_block * kWave);
     const int mode = lds_words == 0 ? 0 : (max_n <= lds_words ? 1 : 2);
-    const size_t shmem = mode == 0 ? 0 : static_cast<size_t>(waves_per_block) * kWave * (lds_words + 4) * sizeof(int32_t);
     const uint32_t P = mode == 0 ? 0u : lds_words;
+    const uint32_t SPw = slot_words(P, max_n, max_ell);
+    const uint32_t TL = (mode == 1 && SPw > P + 4u) ? SPw - P - 4u : 0u;
+    const size_t shmem = mode == 0 ? 0 : static_cast<size_t>(waves_per_block) * kWave * SPw * sizeof(int32_t);
     if (isa == 1) {
-        if (mode == 1) return launch_k3_p<1, 1>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
-        if (mode == 2) return launch_k3_p<1, 2>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
-        return launch_k3_p<1, 0>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+        if (mode == 1 && TL) return launch_k3_p<1, 1, true>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+        if (mode == 1) return launch_k3_p<1, 1, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
+        if (mode == 2) return launch_k3_p<1, 2, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
+        return launch_k3_p<1, 0, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
     }
-    if (mode == 1) return launch_k3_p<0, 1>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
-    if (mode == 2) return launch_k3_p<0, 2>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
-    return launch_k3_p<0, 0>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, q);
+    if (mode == 1 && TL) return launch_k3_p<0, 1, true>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+    if (mode == 1) return launch_k3_p<0, 1, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
+    if (mode == 2) return launch_k3_p<0, 2, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
+    return launch_k3_p<0, 0, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
 }
 
-__global__ void k_zero_queue(QueueState *q)
+__global__ void k_zero_queue(QueueState *q, uint32_t head_only)
 {
-    if (threadIdx.x == 0) { q->head = 0; q->survivors = 0; q->retired = 0; q->pad = 0; }
+    if (threadIdx.x == 0) {
+        q->head = 0;
+        if (!head_only) { q->survivors = 0; q->retired = 0; q->pad = 0; }
+    }
 }
 
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st)
 {
-    k_zero_queue<<<1, 64, 0, st>>>(q);
+    k_zero_queue<<<1, 64, 0, st>>>(q, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_head(QueueState *q, hipStream_t st)
+{
+    k_zero_queue<<<1, 64, 0, st>>>(q, 1u);
     return hipGetLastError();
 }
 
@@ -798,6 +1040,7 @@ hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
     hipError_t e = hipGetLastError();
     if (e) return e;
     k_max_u32<<<256, 256, 0, st>>>(n, N, max_n);
+    k_max_u32<<<256, 256, 0, st>>>(ell, N, max_n + 2);          // max l at max_n[2]
     return hipGetLastError();
 }
 
@@ -806,6 +1049,55 @@ __global__ __launch_bounds__(256) void k_check_state(DevBatch b, uint32_t *err)
     const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= b.N) return;
     if (b.u0[v] > b.ell[v] || b.y0[v] > b.s[v]) atomicOr(err, kErrStateRange);
+    const int32_t i = b.i[v], a = b.a[v];
+    if (sext(static_cast<uint32_t>(i), b.wshift) != i || sext(static_cast<uint32_t>(a), b.wshift) != a)
+        atomicOr(err, kErrWordRange);
+}
+
+// every word a w-bit value: one flag per block, one atomic per offending block
+__global__ __launch_bounds__(256) void k_check_words(const int32_t *__restrict__ w, uint64_t count,
+                                                     uint32_t ws, uint32_t *err)
+{
+    bool bad = false;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < count; k += stride) {
+        const int32_t x = w[k];
+        bad |= sext(static_cast<uint32_t>(x), ws) != x;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(err, kErrWordRange);
+}
+
+// the same over words [off[0], off[N]) of a packed array (offsets in device memory)
+__global__ __launch_bounds__(256) void k_check_words_off(const int32_t *__restrict__ w,
+                                                         const uint64_t *__restrict__ off, uint64_t N,
+                                                         uint32_t ws, uint32_t *err)
+{
+    const uint64_t lo = off[0], hi = off[N];
+    bool bad = false;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t k = lo + static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < hi; k += stride) {
+        const int32_t x = w[k];
+        bad |= sext(static_cast<uint32_t>(x), ws) != x;
+    }
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(err, kErrWordRange);
+}
+
+hipError_t launch_check_words_off(const int32_t *w, const uint64_t *off, uint64_t N, uint32_t wshift,
+                                  uint32_t *err, hipStream_t st)
+{
+    if (wshift == 0) return hipSuccess;
+    k_check_words_off<<<2048, 256, 0, st>>>(w, off, N, wshift, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_words(const int32_t *w, uint64_t count, uint32_t wshift, uint32_t *err,
+                              hipStream_t st)
+{
+    if (count == 0 || wshift == 0) return hipSuccess;
+    uint64_t blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_check_words<<<static_cast<unsigned>(blocks), 256, 0, st>>>(w, count, wshift, err);
+    return hipGetLastError();
 }
 
 hipError_t launch_check_state(DevBatch b, uint32_t *err, hipStream_t st)

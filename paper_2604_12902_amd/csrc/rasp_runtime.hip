@@ -81,7 +81,8 @@ struct Batch {
     Alloc meta, words;
     uint64_t N = 0;
     uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
-    uint32_t max_n = 0;
+    uint32_t max_n = 0, max_ell = 0;
+    uint32_t wbits = 32;                 // word width w
     bool all_pow2 = false;               // every n a power of two
     bool uniform_dense = false;          // every n a multiple of 4: padded == dense
     bool status_stale = true;            // status not yet computed since the load
@@ -151,6 +152,7 @@ struct rasp_ctx {
     // options
     int64_t schedule = RASP_SCHED_AUTO, epoch = 256, lds_words = -1, waves_per_cu = 16, graph = 0;
     int64_t first_pass = 64;
+    int64_t first_pass_kind = 1;         // 1: LDS-resident first pass when memories fit
     // scratch: queue counters, batch tables (device ring + pinned host ring)
     Alloc scratch;
     QueueState *queue = nullptr;
@@ -285,7 +287,7 @@ struct HostShapes {
     std::vector<uint64_t> mem_off, t_off, y_off;
     uint64_t sum_n = 0, sum_n_pad = 0, sum_ell = 0, sum_s = 0;
     uint64_t prog_words = 0, tape_words = 0;
-    uint32_t max_n = 0;
+    uint32_t max_n = 0, max_ell = 0;
     bool all_n_mult4 = true;
     bool all_pow2 = true;
 };
@@ -316,6 +318,7 @@ int host_shapes(rasp_ctx *c, const rasp_batch_desc *d, HostShapes *h)
         if (n & 3u) h->all_n_mult4 = false;
         h->max_n = std::max(h->max_n, n);
         if (n & (n - 1u)) h->all_pow2 = false;
+        h->max_ell = std::max(h->max_ell, static_cast<uint32_t>(ell));
     }
     h->prog_words = d->prog_off[N] - d->prog_off[0];
     h->tape_words = d->tape_off[N] - d->tape_off[0];
@@ -332,7 +335,20 @@ int basic_desc_checks(rasp_ctx *c, const rasp_batch_desc *d)
     if (d->flags & ~(RASP_DESC_DEVICE_PTRS | RASP_DESC_LAZY)) return fail(c, RASP_E_INVAL, "unknown descriptor flags");
     if ((d->flags & RASP_DESC_LAZY) && !(d->flags & RASP_DESC_DEVICE_PTRS))
         return fail(c, RASP_E_INVAL, "RASP_DESC_LAZY needs a device descriptor");
+    if (d->word_bits == 1 || d->word_bits > 32) return fail(c, RASP_E_INVAL, "word_bits %u outside [2, 32]", d->word_bits);
     return RASP_OK;
+}
+
+uint32_t word_bits_of(const rasp_batch_desc *d) { return d->word_bits == 0 ? 32u : d->word_bits; }
+
+// is every host word a w-bit value
+bool host_words_fit(const int32_t *w, uint64_t count, uint32_t bits)
+{
+    if (bits >= 32) return true;
+    const int64_t lo = -(int64_t(1) << (bits - 1)), hi = (int64_t(1) << (bits - 1)) - 1;
+    for (uint64_t k = 0; k < count; ++k)
+        if (w[k] < lo || w[k] > hi) return false;
+    return true;
 }
 
 // Allocate and fill a batch's metadata and word arenas, then queue the pack.
@@ -350,6 +366,8 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         return fail(c, RASP_E_NOMEM, "arena cannot hold state of %llu machines", (unsigned long long)N);
     carve_meta(at<char>(c, B->meta), N, &B->dev);
     B->dev.isa = d->isa;
+    B->wbits = word_bits_of(d);
+    B->dev.wshift = 32u - B->wbits;
 
     const int32_t *prog_dev = nullptr, *tape_dev = nullptr;
     const uint64_t *poff_dev = nullptr, *toff_dev = nullptr;
@@ -368,9 +386,15 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         if ((rc = host_shapes(c, d, &h))) return bail(rc);
         if (h.prog_words && !d->prog) { fail(c, RASP_E_INVAL, "prog is NULL"); return bail(RASP_E_INVAL); }
         if (h.tape_words && !d->tape) { fail(c, RASP_E_INVAL, "tape is NULL"); return bail(RASP_E_INVAL); }
+        if (!host_words_fit(d->prog + d->prog_off[0], h.prog_words, B->wbits) ||
+            !host_words_fit(d->tape + d->tape_off[0], h.tape_words, B->wbits)) {
+            fail(c, RASP_E_INVAL, "a program or input word is not a %u-bit value", B->wbits);
+            return bail(RASP_E_INVAL);
+        }
         B->sum_n = h.sum_n; B->sum_n_pad = h.sum_n_pad; B->sum_ell = h.sum_ell; B->sum_s = h.sum_s;
         B->uniform_dense = h.all_n_mult4;
         B->max_n = h.max_n;
+        B->max_ell = h.max_ell;
         B->all_pow2 = h.all_pow2;
         if (!arena_alloc(c, words_bytes(h.sum_n_pad, h.sum_ell, h.sum_s), &B->words)) {
             fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)h.sum_n);
@@ -465,13 +489,16 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         if (!e) e = launch_scan_u32(B->dev.ell, B->dev.t_off, N, sums + align_up(8 * nsc, kAlign) / 8, &tots[1], st);
         if (!e) e = launch_scan_u32(B->dev.s, B->dev.y_off, N, sums + 2 * align_up(8 * nsc, kAlign) / 8, &tots[2], st);
         if (!e) e = launch_scan_u32(B->dev.n, n_pad, N, sums, &tots[3], st);   // dense total into tots[3]
-        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+        if (!e) e = launch_check_words_off(d->prog, d->prog_off, N, B->dev.wshift, errw, st);
+        if (!e) e = launch_check_words_off(d->tape, d->tape_off, N, B->dev.wshift, errw, st);
+        if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
         if (!e) e = hipStreamSynchronize(st);
         if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         uint32_t errbits;
         std::memcpy(&errbits, reinterpret_cast<char *>(c->tot_host) + 32, 4);
         if (errbits) {
-            fail(c, RASP_E_INVAL, "descriptor check failed (bits 0x%x: 1 offsets, 2 program > memory, 4 input > tape, 8 memory size)", errbits);
+            fail(c, RASP_E_INVAL, "descriptor check failed (bits 0x%x: 1 offsets, 2 program > memory, 4 input > tape, "
+                                  "8 memory size, 32 a word wider than %u bits)", errbits, B->wbits);
             return bail(RASP_E_INVAL);
         }
         B->sum_n_pad = c->tot_host[0]; B->sum_ell = c->tot_host[1]; B->sum_s = c->tot_host[2]; B->sum_n = c->tot_host[3];
@@ -479,6 +506,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         uint32_t nonpow2 = 0;
         std::memcpy(&nonpow2, reinterpret_cast<char *>(c->tot_host) + 40, 4);
         B->all_pow2 = nonpow2 == 0;
+        std::memcpy(&B->max_ell, reinterpret_cast<char *>(c->tot_host) + 44, 4);
         B->uniform_dense = (B->sum_n == B->sum_n_pad);
         if (!arena_alloc(c, words_bytes(B->sum_n_pad, B->sum_ell, B->sum_s), &B->words)) {
             fail(c, RASP_E_NOMEM, "arena cannot hold the batch (%llu memory words)", (unsigned long long)B->sum_n);
@@ -503,7 +531,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
 // LDS words per machine slot for a launch whose largest memory is max_n:
 // the option, or (option -1) the smallest power of two holding the whole
 // memory if two waves of such slots fit a compute unit, else none
-uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n)
+uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n, uint32_t max_ell = 0)
 {
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
     uint32_t P;
@@ -512,9 +540,9 @@ uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n)
     } else {
         P = 4;
         while (P < max_n && P < 1024) P <<= 1;
-        if (P < max_n || 2ull * kWave * (P + 4) * 4 > lds) P = 0;
+        if (P < max_n || 2ull * kWave * slot_words(P, max_n, max_ell) * 4 > lds) P = 0;
     }
-    while (P && static_cast<uint64_t>(kWave) * (P + 4) * 4 > lds) P >>= 1;
+    while (P && static_cast<uint64_t>(kWave) * slot_words(P, max_n, max_ell) * 4 > lds) P >>= 1;
     return P;
 }
 
@@ -571,27 +599,48 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     // lazily loaded batches are built inside the persistent kernel when every
     // machine of the launch fits its LDS slot; otherwise c0 is packed first
     bool any_fresh = false;
-    uint32_t mx = 0;
-    for (uint32_t t = 0; t < k; ++t) { any_fresh |= bs[t]->dev.fresh != 0; mx = std::max(mx, bs[t]->max_n); }
-    const uint32_t Pq = lds_words_for(c, mx);
+    uint32_t mx = 0, mxl = 0;
+    for (uint32_t t = 0; t < k; ++t) {
+        any_fresh |= bs[t]->dev.fresh != 0;
+        mx = std::max(mx, bs[t]->max_n);
+        mxl = std::max(mxl, bs[t]->max_ell);
+    }
+    const uint32_t Pq = lds_words_for(c, mx, mxl);
     const int64_t schedq = c->schedule == RASP_SCHED_AUTO ? RASP_SCHED_PERSISTENT : c->schedule;
-    const bool fused = any_fresh && schedq == RASP_SCHED_PERSISTENT && Pq >= mx;
+    // every memory fits its LDS slot: the persistent kernel can build c0 itself
+    const bool lds_ok = Pq > 0 && Pq >= mx;
+    // the first pass is the persistent kernel in LDS (else the plain kernel)
+    const bool lds_first = schedq == RASP_SCHED_PERSISTENT && c->first_pass > 0 &&
+                           c->first_pass_kind == 1 && lds_ok;
+    // (a) first pass 0 and every memory fits: c0 is built by the persistent
+    //     kernel; (b) an LDS first pass builds c0 the same way; (c) a plain
+    //     first pass packs c0 of its wave's machines before stepping them;
+    //     (d) otherwise pack first.  A batch that runs 0 transitions in the
+    //     launch is never claimed by the persistent kernel: pack it first
+    const bool fused = any_fresh && schedq == RASP_SCHED_PERSISTENT && lds_ok && c->first_pass == 0;
+    const bool pack_in_plain = any_fresh && !fused && !lds_first &&
+                               (schedq == RASP_SCHED_PLAIN || c->first_pass > 0);
     for (uint32_t t = 0; t < k; ++t)
-        if (bs[t]->dev.fresh && (!fused || budgets[t] == 0)) {
+        if (bs[t]->dev.fresh && ((!fused && !lds_first && !pack_in_plain) ||
+                                 ((fused || lds_first) && budgets[t] == 0))) {
             int rc = materialize(c, bs[t]);
             if (rc) return rc;
         }
+    const bool graphed = c->graph && !any_fresh;
     BatchTable *ht, *dt;
     int slot;
     int rc = table_slot(c, &ht, &dt, &slot);
     if (rc) return rc;
     std::memset(ht, 0, sizeof(BatchTable));
     uint64_t total = 0;
-    uint32_t maxb = 0, max_n = 0;
-    bool pow2 = true;
+    uint32_t maxb = 0, max_n = 0, max_ell = 0;
+    bool pow2 = true, wm = false;
     for (uint32_t t = 0; t < k; ++t) {
         max_n = std::max(max_n, bs[t]->max_n);
-        pow2 &= bs[t]->all_pow2;
+        max_ell = std::max(max_ell, bs[t]->max_ell);
+        // v mod n = v & (n - 1) on w-bit words needs n | 2^w
+        pow2 &= bs[t]->all_pow2 && (bs[t]->wbits >= 32 || bs[t]->max_n <= (1u << bs[t]->wbits));
+        wm |= bs[t]->wbits < 32;
         ht->b[t] = bs[t]->dev;
         ht->start[t] = total;
         ht->budget[t] = budgets[t];
@@ -610,14 +659,16 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     hipStream_t st = c->stream;
     int64_t sched = c->schedule;
     if (sched == RASP_SCHED_AUTO) sched = RASP_SCHED_PERSISTENT;
-    if (!(c->graph && !fused)) {
+    if (!graphed) {
         HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
         HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
         c->table_used[slot] = true;
         HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_zero_queue(c->queue, st); }));
     }
-    if (sched == RASP_SCHED_PLAIN && !c->graph) {
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, pow2, nullptr, c->queue, st); }));
+    if (sched == RASP_SCHED_PLAIN && !graphed) {
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
+            return launch_plain(dt, total, maxb, isa, pow2, pack_in_plain, wm, nullptr, c->queue, st); }));
+        for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
         return RASP_OK;
     }
     // persistent: a first plain pass of `first_pass` steps retires the short
@@ -625,20 +676,21 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     // schedule is a first pass as long as the budget)
     const uint32_t cap = sched == RASP_SCHED_PLAIN ? maxb : static_cast<uint32_t>(std::max<int64_t>(0, c->first_pass));
     // waves per block: as many (up to 4) as the LDS slots of one block allow
-    const uint32_t P = lds_words_for(c, max_n);
+    const uint32_t P = lds_words_for(c, max_n, max_ell);
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
+    const uint32_t SPw = slot_words(P, max_n, max_ell);
     uint32_t wpb = 4;
-    while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * (P + 4) * 4 > lds) wpb >>= 1;
+    while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * SPw * 4 > lds) wpb >>= 1;
     const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
     const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
     const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
-    if (c->graph && !fused) {
+    if (graphed) {
         // replay (capturing on first use) the launch sequence for this key
         std::vector<uint64_t> key;
         for (uint32_t t = 0; t < k; ++t) { key.push_back(reinterpret_cast<uint64_t>(bs[t])); key.push_back(budgets[t]); }
         const uint64_t knobs[] = {static_cast<uint64_t>(c->schedule), P, epoch, cap, wpb, blocks,
-                                  pow2 ? 1u : 0u, isa, maxb};
-        key.insert(key.end(), knobs, knobs + 9);
+                                  pow2 ? 1u : 0u, isa, maxb, wm ? 1u : 0u, lds_first ? 1u : 0u};
+        key.insert(key.end(), knobs, knobs + 11);
         rasp_ctx::GraphEntry *ge = nullptr;
         for (auto &g : c->graphs) if (g.key == key) ge = &g;
         if (!ge) {
@@ -653,13 +705,17 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
             hipGraph_t graph = nullptr;
             HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t e = launch_zero_queue(c->queue, st);
-            if (!e && cap > 0 && cap < maxb) {
-                e = launch_plain(gt, total, cap, isa, pow2, work, c->queue, st);
-                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st);
-            } else if (!e && cap >= maxb) {
-                e = launch_plain(gt, total, maxb, isa, pow2, nullptr, c->queue, st);
+            if (!e && cap > 0 && cap < maxb && lds_first) {
+                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, cap, work, c->queue, st);
+                if (!e) e = launch_reset_head(c->queue, st);
+                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st);
+            } else if (!e && cap > 0 && cap < maxb) {
+                e = launch_plain(gt, total, cap, isa, pow2, false, wm, work, c->queue, st);
+                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st);
+            } else if (!e && cap >= maxb && !lds_first) {
+                e = launch_plain(gt, total, maxb, isa, pow2, false, wm, nullptr, c->queue, st);
             } else if (!e) {
-                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st);
+                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st);
             }
             hipError_t e2 = hipStreamEndCapture(st, &graph);
             if (!e) e = e2;
@@ -677,19 +733,44 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     if (fused) {
         // fresh batches present: one persistent launch over every machine
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, nullptr, 0, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st); }));
+            return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st); }));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     } else if (cap > 0 && cap < maxb) {
         if ((rc = ensure_work(c, total))) return rc;
         uint32_t *work = at<uint32_t>(c, c->work);
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, cap, isa, pow2, work, c->queue, st); }));
+        if (lds_first) {
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_FIRST, [&] {
+                return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, cap, work, c->queue, st); }));
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_reset_head(c->queue, st); }));
+        } else {
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
+                return launch_plain(dt, total, cap, isa, pow2, pack_in_plain, wm, work, c->queue, st); }));
+        }
+        BatchTable *dt2 = dt;
+        if (any_fresh) {
+            // the survivors' c0 now sits in the arena: their table says so
+            BatchTable *ht2;
+            int slot2;
+            if ((rc = table_slot(c, &ht2, &dt2, &slot2))) return rc;
+            std::memcpy(ht2, ht, sizeof(BatchTable));
+            for (uint32_t t = 0; t < k; ++t) ht2->b[t].fresh = 0;
+            HIPCHK(c, hipMemcpyAsync(dt2, ht2, sizeof(BatchTable), hipMemcpyHostToDevice, st));
+            HIPCHK(c, hipEventRecord(c->table_ev[slot2], st));
+            c->table_used[slot2] = true;
+        }
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, work, cap, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st); }));
-    } else if (cap >= maxb) {
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] { return launch_plain(dt, total, maxb, isa, pow2, nullptr, c->queue, st); }));
+            return launch_persistent(dt2, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st); }));
+        for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
+    } else if (cap >= maxb && !lds_first) {
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
+            return launch_plain(dt, total, maxb, isa, pow2, pack_in_plain, wm, nullptr, c->queue, st); }));
+        for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     } else {
+        // no first pass (or one as long as the budget): one persistent launch;
+        // fresh machines here fit their slots and are built by the kernel
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, nullptr, 0, isa, pow2, epoch, P, max_n, wpb, blocks, c->queue, st); }));
+            return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st); }));
+        for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     }
     return RASP_OK;
 }
@@ -877,12 +958,15 @@ int rasp_load_state(rasp_ctx *c, const rasp_batch_desc *d, const rasp_outputs *s
     uint32_t *derr = reinterpret_cast<uint32_t *>(&c->queue->pad);
     if (!e) e = hipMemsetAsync(derr, 0, 4, st);
     if (!e) e = launch_check_state(b.dev, derr, st);
+    if (!e) e = launch_check_words(b.dev.M, b.sum_n_pad, b.dev.wshift, derr, st);
+    if (!e) e = launch_check_words(b.dev.Y, b.sum_s, b.dev.wshift, derr, st);
     if (!e) e = launch_probe(b.dev, st);
     if (!e) b.status_stale = false;
     if (!e) e = hipMemcpyAsync(errw, derr, 4, hipMemcpyDeviceToHost, st);
     if (!e) e = hipStreamSynchronize(st);
     if (e) { fail(c, RASP_E_DEVICE, "state load: %s", hipGetErrorString(e)); return undo(RASP_E_DEVICE); }
-    if (*errw) { fail(c, RASP_E_INVAL, "state has u0 > l or y0 > s"); return undo(RASP_E_INVAL); }
+    if (*errw & kErrStateRange) { fail(c, RASP_E_INVAL, "state has u0 > l or y0 > s"); return undo(RASP_E_INVAL); }
+    if (*errw) { fail(c, RASP_E_INVAL, "a word of the state is not a %u-bit value", b.wbits); return undo(RASP_E_INVAL); }
     arena_free(c, &tmp);
     const rasp_batch h = c->next_handle++;
     c->batches[h] = std::move(B);
@@ -1106,6 +1190,9 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
         c->first_pass = value; return RASP_OK;
     case RASP_OPT_PROFILE:
         c->profile = value ? 1 : 0; return RASP_OK;
+    case RASP_OPT_FIRST_PASS_KIND:
+        if (value != 0 && value != 1) return fail(c, RASP_E_INVAL, "first pass kind must be 0 or 1");
+        c->first_pass_kind = value; return RASP_OK;
     default:
         return fail(c, RASP_E_INVAL, "unknown option %d", option);
     }
@@ -1122,6 +1209,7 @@ int rasp_get_option(rasp_ctx *c, int option, int64_t *value)
     case RASP_OPT_GRAPH: *value = c->graph; return RASP_OK;
     case RASP_OPT_FIRST_PASS: *value = c->first_pass; return RASP_OK;
     case RASP_OPT_PROFILE: *value = c->profile; return RASP_OK;
+    case RASP_OPT_FIRST_PASS_KIND: *value = c->first_pass_kind; return RASP_OK;
     default: return fail(c, RASP_E_INVAL, "unknown option %d", option);
     }
 }
@@ -1152,7 +1240,9 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     if (rc) return rc;
     Batch *b = find(c, h);
     if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
-    if ((rc = materialize(c, b))) return rc;
+    // a lazily loaded batch stays lazy: every trial rebuilds c0 of the prefix
+    // from the caller's descriptor arrays, as the real run will
+    const bool lazy = b->dev.fresh != 0;
     hipStream_t st = c->stream;
     const uint64_t K = (max_vms == 0 || max_vms > b->N) ? b->N : max_vms;
     const uint32_t bud = static_cast<uint32_t>(std::min<uint64_t>(budget, 0x7fffffffull));
@@ -1167,13 +1257,17 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     HIPCHK(c, hipMemcpyAsync(&ss, b->dev.s + K - 1, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     const uint64_t m_end = mo + ((nn + 3ull) & ~3ull), t_end = to + el, y_end = yo + ss;
-    // snapshot (restore source) and trial batch, both K machines
+    // snapshot (restore source) and trial batch, both K machines; a lazy
+    // batch needs no snapshot (its c0 is rebuilt from the descriptor)
     Batch snap, trial;
-    for (Batch *x : {&snap, &trial}) {
+    std::vector<Batch *> parts = {&trial};
+    if (!lazy) parts.push_back(&snap);
+    for (Batch *x : parts) {
         *x = Batch();
         x->N = K;
         x->sum_n_pad = m_end; x->sum_ell = t_end; x->sum_s = y_end;
-        x->max_n = b->max_n; x->all_pow2 = b->all_pow2; x->status_stale = b->status_stale;
+        x->max_n = b->max_n; x->max_ell = b->max_ell; x->all_pow2 = b->all_pow2; x->status_stale = b->status_stale;
+        x->wbits = b->wbits;
         if (!arena_alloc(c, meta_bytes(K), &x->meta) || !arena_alloc(c, words_bytes(m_end, t_end, y_end), &x->words)) {
             arena_free(c, &snap.meta); arena_free(c, &snap.words);
             arena_free(c, &trial.meta); arena_free(c, &trial.words);
@@ -1182,8 +1276,21 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         carve_meta(at<char>(c, x->meta), K, &x->dev);
         carve_words(at<char>(c, x->words), m_end, t_end, &x->dev);
         x->dev.isa = b->dev.isa;
+        x->dev.wshift = b->dev.wshift;
         x->dev.fresh = 0;
+        x->dev.prog = b->dev.prog; x->dev.prog_off = b->dev.prog_off;
+        x->dev.tape = b->dev.tape; x->dev.tape_off = b->dev.tape_off;
     }
+    auto copy_shapes = [&](const DevBatch &src, const DevBatch &dst) -> hipError_t {
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        hipError_t e = hipMemcpyAsync(dst.n, src.n, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.ell, src.ell, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.s, src.s, 4 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.mem_off, src.mem_off, 8 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.t_off, src.t_off, 8 * K, k, st);
+        if (!e) e = hipMemcpyAsync(dst.y_off, src.y_off, 8 * K, k, st);
+        return e;
+    };
     auto copy_batch = [&](const DevBatch &src, const DevBatch &dst) -> hipError_t {
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
         hipError_t e = hipMemcpyAsync(dst.i, src.i, 4 * K, k, st);
@@ -1192,12 +1299,7 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         if (!e) e = hipMemcpyAsync(dst.y0, src.y0, 4 * K, k, st);
         if (!e) e = hipMemcpyAsync(dst.steps, src.steps, 8 * K, k, st);
         if (!e) e = hipMemcpyAsync(dst.status, src.status, K, k, st);
-        if (!e) e = hipMemcpyAsync(dst.n, src.n, 4 * K, k, st);
-        if (!e) e = hipMemcpyAsync(dst.ell, src.ell, 4 * K, k, st);
-        if (!e) e = hipMemcpyAsync(dst.s, src.s, 4 * K, k, st);
-        if (!e) e = hipMemcpyAsync(dst.mem_off, src.mem_off, 8 * K, k, st);
-        if (!e) e = hipMemcpyAsync(dst.t_off, src.t_off, 8 * K, k, st);
-        if (!e) e = hipMemcpyAsync(dst.y_off, src.y_off, 8 * K, k, st);
+        if (!e) e = copy_shapes(src, dst);
         if (!e) e = hipMemcpyAsync(dst.M, src.M, 4 * m_end, k, st);
         if (!e && t_end) e = hipMemcpyAsync(dst.T, src.T, 4 * t_end, k, st);
         if (!e && y_end) e = hipMemcpyAsync(dst.Y, src.Y, 4 * y_end, k, st);
@@ -1208,18 +1310,23 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         arena_free(c, &snap.meta); arena_free(c, &snap.words);
         arena_free(c, &trial.meta); arena_free(c, &trial.words);
     };
-    hipError_t e = copy_batch(b->dev, snap.dev);
+    hipError_t e = lazy ? copy_shapes(b->dev, trial.dev) : copy_batch(b->dev, snap.dev);
     if (e) { release(); return fail(c, RASP_E_DEVICE, "autotune snapshot: %s", hipGetErrorString(e)); }
-    const int64_t saved[] = {c->schedule, c->lds_words, c->first_pass, c->epoch, c->waves_per_cu, c->graph, c->profile};
+    const int64_t saved[] = {c->schedule, c->lds_words, c->first_pass, c->epoch, c->waves_per_cu,
+                             c->first_pass_kind, c->graph, c->profile};
     c->graph = 0;
     c->profile = 0;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     auto trial_ms = [&](double *ms) -> int {
-        hipError_t x = copy_batch(snap.dev, trial.dev);
-        if (x) return fail(c, RASP_E_DEVICE, "autotune restore: %s", hipGetErrorString(x));
-        trial.status_stale = snap.status_stale;
+        if (lazy) {
+            trial.dev.fresh = 1;
+        } else {
+            hipError_t x = copy_batch(snap.dev, trial.dev);
+            if (x) return fail(c, RASP_E_DEVICE, "autotune restore: %s", hipGetErrorString(x));
+            trial.status_stale = snap.status_stale;
+        }
         Batch *tb = &trial;
         HIPCHK(c, hipEventRecord(e0, st));
         int r2 = run_batches(c, &tb, &bud, 1);
@@ -1235,23 +1342,30 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     const int64_t full = [&]() { int64_t P = 4; while (P < b->max_n && P < 1024) P <<= 1; return P; }();
     std::vector<int64_t> lds_c = {0, 32, 64, 128, 256};
     if (full <= 1024 && std::find(lds_c.begin(), lds_c.end(), full) == lds_c.end()) lds_c.push_back(full);
-    const std::vector<int64_t> fp_c = {0, 16, 64, 256}, ep_c = {64, 256, 1024}, wv_c = {8, 16, 32};
-    int64_t cur[5] = {RASP_SCHED_PERSISTENT, c->lds_words < 0 ? static_cast<int64_t>(lds_words_for(c, b->max_n)) : c->lds_words,
-                      c->first_pass, c->epoch, c->waves_per_cu};
+    const std::vector<int64_t> fp_c = {0, 16, 64, 256}, ep_c = {16, 64, 256, 1024}, wv_c = {8, 16, 32},
+                               fk_c = {0, 1};
+    int64_t cur[6] = {RASP_SCHED_PERSISTENT, c->lds_words < 0 ? static_cast<int64_t>(lds_words_for(c, b->max_n, b->max_ell)) : c->lds_words,
+                      c->first_pass, c->epoch, c->waves_per_cu, c->first_pass_kind};
     auto apply = [&](const int64_t *o) {
         c->schedule = o[0]; c->lds_words = o[1]; c->first_pass = o[2]; c->epoch = o[3]; c->waves_per_cu = o[4];
+        c->first_pass_kind = o[5];
     };
     double best = 1e30;
     apply(cur);
     rc = trial_ms(&best);
     // warm-up run above; measure the starting point again
     if (!rc) rc = trial_ms(&best);
-    const std::vector<int64_t> *lists[5] = {nullptr, &lds_c, &fp_c, &ep_c, &wv_c};
-    for (int knob = 1; knob <= 4 && !rc; ++knob) {
+    const std::vector<int64_t> *lists[6] = {nullptr, &lds_c, &fp_c, &ep_c, &wv_c, &fk_c};
+    // the first-pass kind first: it changes which lengths and epochs pay
+    const int order[] = {1, 5, 2, 3, 4};
+    for (int oi = 0; oi < 5 && !rc; ++oi) {
+        const int knob = order[oi];
         for (int64_t val : *lists[knob]) {
             if (val == cur[knob]) continue;
-            if (knob == 1 && val > 0 && static_cast<uint64_t>(kWave) * (val + 4) * 4 > static_cast<uint64_t>(c->lds_bytes)) continue;
-            int64_t o[5] = {cur[0], cur[1], cur[2], cur[3], cur[4]};
+            if (knob == 1 && val > 0 &&
+                static_cast<uint64_t>(kWave) * slot_words(static_cast<uint32_t>(val), b->max_n, b->max_ell) * 4 >
+                    static_cast<uint64_t>(c->lds_bytes)) continue;
+            int64_t o[6] = {cur[0], cur[1], cur[2], cur[3], cur[4], cur[5]};
             o[knob] = val;
             apply(o);
             double ms = 0;
@@ -1260,7 +1374,7 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         }
     }
     if (!rc) {                              // the plain schedule as a whole
-        int64_t o[5] = {RASP_SCHED_PLAIN, cur[1], cur[2], cur[3], cur[4]};
+        int64_t o[6] = {RASP_SCHED_PLAIN, cur[1], cur[2], cur[3], cur[4], cur[5]};
         apply(o);
         double ms = 0;
         rc = trial_ms(&ms);
@@ -1269,15 +1383,15 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release();
-    c->graph = saved[5];
-    c->profile = saved[6];
+    c->graph = saved[6];
+    c->profile = saved[7];
     if (rc) {
-        const int64_t back[5] = {saved[0], saved[1], saved[2], saved[3], saved[4]};
+        const int64_t back[6] = {saved[0], saved[1], saved[2], saved[3], saved[4], saved[5]};
         apply(back);
         return rc;
     }
     apply(cur);
-    if (chosen) for (int q = 0; q < 5; ++q) chosen[q] = cur[q];
+    if (chosen) for (int q = 0; q < 6; ++q) chosen[q] = cur[q];
     if (best_ms) *best_ms = best;
     return RASP_OK;
 }

@@ -153,12 +153,17 @@ class Layout:
 
     Cell 2m + 0 is the reserved nu; cells 2m+1..2m+4 are left reserved (the
     paper budgets 5 reserved words); then ipt (l words), opt (s words) and scr
-    (mu words).  Array indexing is modulo the declared length."""
+    (mu words).  Array indexing is modulo the array's length.  Sec. 2.2 types
+    the arrays as ipt : W^(k <= l) and opt : W^(e <= s); a program that declares
+    more (the grammar allows arities up to 9) gets the region's size, so the
+    regions stay disjoint: |ipt| = min(declared, l), |opt| = min(declared, s)."""
 
     def __init__(self, n_in, n_out, ell, s, mu):
+        if ell < 1 or s < 1 or mu < 1:
+            raise ValueError("the ipt, opt and scr regions need at least one word each")
         self.n_in, self.n_out, self.ell, self.s, self.mu = n_in, n_out, ell, s, mu
         self.base = {"ipt": 5, "opt": 5 + ell, "scr": 5 + ell + s}
-        self.length = {"ipt": n_in, "opt": n_out, "scr": mu}
+        self.length = {"ipt": min(n_in, ell), "opt": min(n_out, s), "scr": mu}
 
     def offset(self, arr, z):
         return self.base[arr] + (z % self.length[arr])
@@ -168,11 +173,14 @@ class Layout:
         return 5 + self.ell + self.s + self.mu
 
 
-def lower_word(fun, ell=10, s=2, mu=10):
+def lower_word(fun, ell=10, s=2, mu=10, read_inputs=False):
     """Lower a parsed program to word-RASP (opcode, operand) pairs.
 
     Returns (pairs, layout).  Operands are resolved to absolute word addresses
-    (instruction k sits at words 2k, 2k+1; a jump target is a word address)."""
+    (instruction k sits at words 2k, 2k+1; a jump target is a word address).
+    With read_inputs, a prologue ``RD ipt[k]`` for k < |ipt| moves the input
+    word x_k from the tape (where c0 of Sec. 2.1 puts x) into the ipt region;
+    without it ipt stays zero, as in the App. B search."""
     _, n_in, n_out, body = fun
     lay = Layout(n_in, n_out, ell, s, mu)
     code = []           # items: (op, operand) with operand int | ('d', off) | ('L', id)
@@ -193,7 +201,7 @@ def lower_word(fun, ell=10, s=2, mu=10):
         emit(W_LOD, 1); emit(W_BNZ, ("L", lbl))
 
     def hlt():                          # PRI q_i for every output, then HLT = 0 0
-        for q in range(n_out):
+        for q in range(lay.length["opt"]):
             emit(W_PRI, ("d", lay.offset("opt", q)))
         emit(0, 0)
 
@@ -235,6 +243,9 @@ def lower_word(fun, ell=10, s=2, mu=10):
         else:
             raise ValueError(kind)
 
+    if read_inputs:
+        for k in range(lay.length["ipt"]):
+            emit(W_RD, ("d", lay.offset("ipt", k)))
     block(body)
     hlt()                               # Fun: C PRI q_0..q_{l-1} HLT
     m = len(code)

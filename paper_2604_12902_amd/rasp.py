@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librasp.so")
 
-RASP_ABI_VERSION = 1
+RASP_ABI_VERSION = 2
 RASP_OK, RASP_E_INVAL, RASP_E_NOMEM, RASP_E_DEVICE, RASP_E_STATE, RASP_E_BUSY = 0, -1, -2, -3, -4, -5
 RASP_ISA_WORD, RASP_ISA_CLASSIC = 0, 1
 RASP_RUNNING, RASP_HALTED = 0, 1
@@ -31,7 +31,8 @@ RASP_OPT_SCHEDULE, RASP_OPT_EPOCH, RASP_OPT_LDS_WORDS = 1, 2, 3
 RASP_OPT_WAVES_PER_CU, RASP_OPT_GRAPH, RASP_OPT_FIRST_PASS = 4, 5, 6
 RASP_SCHED_AUTO, RASP_SCHED_PLAIN, RASP_SCHED_PERSISTENT = 0, 1, 2
 RASP_OPT_PROFILE = 7
-KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other")
+RASP_OPT_FIRST_PASS_KIND = 8
+KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other", "first")
 
 EXPORTED = ("rasp_create", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi",
@@ -52,7 +53,7 @@ class rasp_batch_desc(ctypes.Structure):
                 ("prog", P), ("prog_off", P), ("mem_words", P),
                 ("default_mem_words", ctypes.c_uint32), ("default_out_cap", ctypes.c_uint32),
                 ("tape", P), ("tape_off", P), ("tape_cap", P), ("out_cap", P),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("word_bits", ctypes.c_uint32)]
 
 
 class rasp_outputs(ctypes.Structure):
@@ -147,15 +148,16 @@ def make_desc(batch, device=None, lazy: bool = False) -> Desc:
         arrs = {k: torch.from_numpy(v.view(signed.get(v.dtype, v.dtype))).to(device)
                 for k, v in arrs.items()}
         flags = RASP_DESC_DEVICE_PTRS | (RASP_DESC_LAZY if lazy else 0)
-    return desc_from_arrays(batch.isa, batch.N, flags=flags, **arrs)
+    return desc_from_arrays(batch.isa, batch.N, flags=flags,
+                            word_bits=getattr(batch, "word_bits", 32), **arrs)
 
 
 def desc_from_arrays(isa, num_vms, prog, prog_off, tape, tape_off, mem_words=None,
                      default_mem_words=0, tape_cap=None, out_cap=None, default_out_cap=0,
-                     flags=0) -> Desc:
+                     flags=0, word_bits=32) -> Desc:
     c = rasp_batch_desc(RASP_ABI_VERSION, isa, num_vms, _ptr(prog), _ptr(prog_off),
                         _ptr(mem_words), default_mem_words, default_out_cap, _ptr(tape),
-                        _ptr(tape_off), _ptr(tape_cap), _ptr(out_cap), flags, 0)
+                        _ptr(tape_off), _ptr(tape_cap), _ptr(out_cap), flags, word_bits)
     return Desc(c, (prog, prog_off, mem_words, tape, tape_off, tape_cap, out_cap))
 
 
@@ -270,12 +272,13 @@ def rasp_running_counts(ctx, batches) -> np.ndarray:
     return out
 
 
-AUTOTUNE_KNOBS = ("schedule", "lds_words", "first_pass", "epoch", "waves_per_cu")
+AUTOTUNE_KNOBS = ("schedule", "lds_words", "first_pass", "epoch", "waves_per_cu",
+                  "first_pass_kind")
 
 
 def rasp_autotune(ctx, batch: int, budget: int, max_vms: int = 0) -> dict:
     """Pick and set the scheduling knobs for batches shaped like `batch`."""
-    chosen = np.zeros(5, np.int64)
+    chosen = np.zeros(len(AUTOTUNE_KNOBS), np.int64)
     best = ctypes.c_double()
     _check(_lib.rasp_autotune(ctx, batch, budget, max_vms, _ptr(chosen), ctypes.byref(best)), ctx)
     out = {k: int(v) for k, v in zip(AUTOTUNE_KNOBS, chosen)}

@@ -19,11 +19,12 @@ from __future__ import annotations
 
 import hashlib
 import math
+import random
 from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import dsl
+from . import dsl, grammar
 
 ISA_WORD = 0
 ISA_CLASSIC = 1
@@ -56,6 +57,7 @@ class Batch:
     budget: int = 0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    word_bits: int = 32               # w of Sec. 2.1: words are w-bit, sign-extended
 
     @property
     def N(self) -> int:
@@ -64,6 +66,8 @@ class Batch:
     def sha256(self) -> str:
         h = hashlib.sha256()
         h.update(np.int64(self.isa).tobytes())
+        if self.word_bits != 32:
+            h.update(np.int64(self.word_bits).tobytes())
         for arr in (self.prog, self.prog_off, self.mem_words, self.tape,
                     self.tape_off, self.tape_cap, self.out_cap):
             h.update(np.ascontiguousarray(arr).tobytes())
@@ -79,7 +83,7 @@ class Batch:
         return Batch(self.isa, prog, _offsets(plen), self.mem_words[idx].copy(),
                      tape, _offsets(tlen), self.tape_cap[idx].copy(),
                      self.out_cap[idx].copy(), self.budget, self.name + "[subset]",
-                     dict(self.meta))
+                     dict(self.meta), self.word_bits)
 
     def footprint_words(self) -> int:
         return int(self.mem_words.astype(np.int64).sum() + self.tape_cap.astype(np.int64).sum()
@@ -343,6 +347,64 @@ def config4(seed: int = 3, num_vms: int = 1 << 18, num_distinct: int = 2048,
                  np.full(num_vms, ROLLOUT_OUT, np.uint32), budget=budget,
                  name="rollouts 256Kx[128,384] n=2048 budget=2^20",
                  meta=dict(seed=seed, num_distinct=len(progs)))
+
+
+# ---- Sec. 3: uniform Sec. 2.2 programs of exactly L terminals (Fig. 1 workload) ----
+
+FIG1_L = 100
+FIG1_N, FIG1_ELL, FIG1_S, FIG1_MU = 250, 10, 2, 10
+FIG1_BUDGET = 10 ** 6
+
+
+def fig1_source(seed: int, index: int, L: int = FIG1_L) -> str:
+    """Source text of program `index` of the family `seed` (independent of N):
+    uniform over the Sec. 2.2 programs of exactly L terminals, drawn from
+    Python's Mersenne Twister seeded with seed * 2^40 + index."""
+    return grammar.sample_program(L, random.Random(seed * (1 << 40) + index))
+
+
+def _fig1_chunk(job):
+    seed, start, stop, L = job
+    progs, arity = [], []
+    for v in range(start, stop):
+        pairs, lay = dsl.lower_word(dsl.parse(fig1_source(seed, v, L)), ell=FIG1_ELL, s=FIG1_S,
+                                    mu=FIG1_MU, read_inputs=True)
+        if 2 * len(pairs) + lay.data_words > FIG1_N:
+            raise RuntimeError("program %d does not fit n = %d" % (v, FIG1_N))
+        progs.append(np.array(dsl.flatten(pairs), dtype=np.int32))
+        arity.append(lay.length["ipt"])
+    return progs, arity
+
+
+def fig1(seed: int = 5, num_vms: int = 1 << 18, L: int = FIG1_L, budget: int = FIG1_BUDGET,
+         workers: int = 1) -> Batch:
+    """The Sec. 3 evaluation: word-RASP machines with w = 32, n = 250, l = 10,
+    s = 2, each running a program drawn uniformly from the Sec. 2.2 snippets of
+    exactly L = 100 terminals (``grammar``), lowered by the Sec. 2.2 rules with
+    scr of mu = 10 words and a prologue that READs the input into ipt.  The
+    input x is arity(P) words uniform over all 2^32 values (x ~ F_2^(w arity)),
+    from PCG64(seed) in machine order; budget tau_max = 10^6.  Programs are
+    generated in chunks of 4,096 (in `workers` spawned processes when it is
+    above 1, which needs a __main__ that is a file; the result does not
+    depend on it)."""
+    chunk = 4096
+    jobs = [(seed, a, min(num_vms, a + chunk), L) for a in range(0, num_vms, chunk)]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            parts = pool.map(_fig1_chunk, jobs)
+    else:
+        parts = [_fig1_chunk(j) for j in jobs]
+    progs = [p for part in parts for p in part[0]]
+    arity = np.array([a for part in parts for a in part[1]], dtype=np.int64)
+    plen = np.array([len(p) for p in progs], dtype=np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    tape = rng.integers(-(1 << 31), 1 << 31, size=int(arity.sum()), dtype=np.int64).astype(np.int32)
+    return Batch(ISA_WORD, np.concatenate(progs), _offsets(plen),
+                 np.full(num_vms, FIG1_N, np.uint32), tape, _offsets(arity),
+                 np.full(num_vms, FIG1_ELL, np.uint32), np.full(num_vms, FIG1_S, np.uint32),
+                 budget=budget, name="fig1 %d x L=%d n=250 budget=10^6" % (num_vms, L),
+                 meta=dict(seed=seed, L=L))
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}

@@ -57,3 +57,21 @@ def test_footprint_is_pure_and_checks_descriptors():
         raise AssertionError("expected RASP_E_INVAL")
     except rasp.RaspError as e:
         assert e.code == rasp.RASP_E_INVAL
+
+
+def test_binding_constants_match_the_header():
+    """Every RASP_* constant of the header has the same value in the binding."""
+    from paper_2604_12902_amd import rasp
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(RASP_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    m = re.search(r"#define\s+RASP_ABI_VERSION\s+(\d+)u", src)
+    consts["RASP_ABI_VERSION"] = int(m.group(1))
+    assert len(consts) > 30
+    for name, value in consts.items():
+        if name.startswith("RASP_KERNEL_"):
+            continue
+        assert getattr(rasp, name) == value, name
+    kinds = {n: v for n, v in consts.items() if n.startswith("RASP_KERNEL_") and n != "RASP_KERNEL_COUNT"}
+    assert consts["RASP_KERNEL_COUNT"] == len(rasp.KERNEL_NAMES) == len(kinds)
+    for n, v in kinds.items():
+        assert rasp.KERNEL_NAMES[v] == n[len("RASP_KERNEL_"):].lower(), n

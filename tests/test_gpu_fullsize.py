@@ -79,3 +79,19 @@ def test_rollouts_full_size_sampled(R):
     _check_sample(b, got, idx)
     # every rollout program halts well inside its budget
     assert (got["status"] == 1).all()
+
+
+def test_fig1_workload_sampled(R):
+    """The Sec. 3 evaluation's shape: uniform L = 100 programs, word RASP,
+    n = 250 (not a power of two), budget 10^6; 65,536 machines, a seeded
+    sample plus the first 2,000 machines."""
+    b = W.fig1(num_vms=1 << 16)
+    print("case: fig1 N=%d" % b.N, flush=True)
+    got, info = _run(R, b)
+    rng = np.random.Generator(np.random.PCG64(9))
+    idx = np.unique(np.concatenate([np.sort(rng.choice(b.N, 1500, replace=False)),
+                                    np.arange(2000)]))
+    _check_sample(b, got, idx)
+    assert (got["steps"] <= b.budget).all() and (got["u0"] <= 10).all()
+    assert ((got["status"] == 1) | (got["steps"] == b.budget)).all()
+    assert info["steps_sum"] == int(got["steps"].sum())

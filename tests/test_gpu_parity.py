@@ -15,12 +15,16 @@ from paper_2604_12902_amd import dsl, workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+# kind 0: the first pass is the plain kernel; kind 1: the persistent kernel
+# with memory in LDS (when every memory fits its slot, else the plain kernel)
 SCHEDULES = {
     "plain": dict(schedule=1),
-    "persistent-hbm": dict(schedule=2, first_pass=0, lds_words=0, epoch=16),
-    "persistent-lds32": dict(schedule=2, first_pass=0, lds_words=32, epoch=8),
-    "firstpass-lds64": dict(schedule=2, first_pass=4, lds_words=64, epoch=32),
-    "firstpass-lds16-tiny-epoch": dict(schedule=2, first_pass=1, lds_words=16, epoch=1),
+    "persistent-hbm": dict(schedule=2, first_pass=0, lds_words=0, epoch=16, kind=1),
+    "persistent-lds32": dict(schedule=2, first_pass=0, lds_words=32, epoch=8, kind=1),
+    "firstpass-lds64": dict(schedule=2, first_pass=4, lds_words=64, epoch=32, kind=0),
+    "firstpass-lds16-tiny-epoch": dict(schedule=2, first_pass=1, lds_words=16, epoch=1, kind=0),
+    "ldsfirst-lds64": dict(schedule=2, first_pass=5, lds_words=64, epoch=32, kind=1),
+    "ldsfirst-lds1024-epoch3": dict(schedule=2, first_pass=7, lds_words=1024, epoch=3, kind=1),
 }
 
 
@@ -46,6 +50,7 @@ def configure(ctx, rasp, sched):
         ctx.set(rasp.RASP_OPT_FIRST_PASS, o["first_pass"])
         ctx.set(rasp.RASP_OPT_LDS_WORDS, o["lds_words"])
         ctx.set(rasp.RASP_OPT_EPOCH, o["epoch"])
+        ctx.set(rasp.RASP_OPT_FIRST_PASS_KIND, o["kind"])
 
 
 def compare(got, want: oracle.State, mem=True, idx=None):
@@ -132,7 +137,7 @@ def test_busy_beavers_word_set(ctx, rasp):
     assert (got["status"] == 1).all()
 
 
-@pytest.mark.parametrize("sched", ["plain", "firstpass-lds64"])
+@pytest.mark.parametrize("sched", ["plain", "firstpass-lds64", "ldsfirst-lds1024-epoch3"])
 def test_uneven_batch_reduced_bit_exact(ctx, rasp, sched):
     print("case: uneven N=20000 sched=%s" % sched, flush=True)
     configure(ctx, rasp, sched)
@@ -190,7 +195,8 @@ def _random_states(b, seed):
     return st
 
 
-@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "firstpass-lds16-tiny-epoch"])
+@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "firstpass-lds16-tiny-epoch",
+                                   "ldsfirst-lds64"])
 @pytest.mark.parametrize("isa", [0, 1])
 def test_loaded_states_fuzz(ctx, rasp, sched, isa):
     """rasp_load_state with arbitrary configurations (i near INT32_MAX, odd,
@@ -377,7 +383,8 @@ def test_autotune_leaves_the_batch_and_stays_bit_exact(ctx, rasp):
     for k in R.AUTOTUNE_KNOBS:
         assert ctx.get({"schedule": R.RASP_OPT_SCHEDULE, "lds_words": R.RASP_OPT_LDS_WORDS,
                         "first_pass": R.RASP_OPT_FIRST_PASS, "epoch": R.RASP_OPT_EPOCH,
-                        "waves_per_cu": R.RASP_OPT_WAVES_PER_CU}[k]) == chosen[k]
+                        "waves_per_cu": R.RASP_OPT_WAVES_PER_CU,
+                        "first_pass_kind": R.RASP_OPT_FIRST_PASS_KIND}[k]) == chosen[k]
     after = ctx.fetch(h, mem=True)
     for k in before:
         assert np.array_equal(before[k], after[k]), k
@@ -390,3 +397,112 @@ def test_autotune_leaves_the_batch_and_stays_bit_exact(ctx, rasp):
     ctx.set(R.RASP_OPT_FIRST_PASS, 64)
     ctx.set(R.RASP_OPT_EPOCH, 256)
     ctx.set(R.RASP_OPT_WAVES_PER_CU, 16)
+    ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 1)
+
+
+def test_autotune_on_a_lazy_batch(ctx, rasp):
+    """Tuning a lazily loaded batch leaves it lazy: its first real run still
+    builds c0 from the descriptor and the result is bit-exact."""
+    R = rasp
+    b = W.config3(num_vms=5000, seed=82, budget=1500)
+    try:
+        h = ctx.load(b, device_desc=True, lazy=True)
+        chosen = R.rasp_autotune(ctx.handle, h, 1500, max_vms=2500)
+        print("autotune (lazy) chose", chosen, flush=True)
+        assert chosen["best_ms"] > 0
+        ctx.run(h, 1500)
+        compare(ctx.fetch(h, mem=True), oracle.run(b, 1500))
+        ctx.free(h)
+    finally:
+        ctx.set(R.RASP_OPT_SCHEDULE, 0)
+        ctx.set(R.RASP_OPT_LDS_WORDS, -1)
+        ctx.set(R.RASP_OPT_FIRST_PASS, 64)
+        ctx.set(R.RASP_OPT_EPOCH, 256)
+        ctx.set(R.RASP_OPT_WAVES_PER_CU, 16)
+        ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 1)
+
+
+@pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "firstpass-lds64", "ldsfirst-lds64"])
+def test_fig1_programs_bit_exact(ctx, rasp, sched):
+    """Word RASP, n = 250 (the general-n path), uniform Sec. 2.2 programs with
+    the input-reading prologue, budget 10^6: every machine."""
+    print("case: fig1 N=2048 sched=%s" % sched, flush=True)
+    configure(ctx, rasp, sched)
+    b = W.fig1(num_vms=2048, seed=12)
+    compare(run_gpu(ctx, b, b.budget), oracle.run(b, b.budget, threads=16))
+
+
+def _to_width(b, w):
+    """The batch with every program and input word reduced to a w-bit value
+    (sign-extended), marked as a w-bit batch."""
+    def red(x):
+        x = x.astype(np.int64) & ((1 << w) - 1)
+        return np.where(x >= 1 << (w - 1), x - (1 << w), x).astype(np.int32)
+    b.prog = red(b.prog)
+    b.tape = red(b.tape)
+    b.word_bits = w
+    return b
+
+
+@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "persistent-hbm",
+                                   "firstpass-lds16-tiny-epoch", "ldsfirst-lds64"])
+@pytest.mark.parametrize("isa", [0, 1])
+@pytest.mark.parametrize("w", [3, 5, 8, 16, 29])
+def test_narrow_words_bit_exact(ctx, rasp, sched, isa, w):
+    """Words of w < 32 bits (Sec. 2.1, W = F_2^w): arithmetic, i + 1 and i + 2
+    wrap mod 2^w; tiny ragged machines whose counters and operands reach the
+    w-bit edges, memory sizes both below and above 2^w."""
+    print("case: narrow words w=%d isa=%d sched=%s" % (w, isa, sched), flush=True)
+    configure(ctx, rasp, sched)
+    b = _to_width(W.tiny_random(seed=300 + w + 50 * isa, num_vms=3000, isa=isa, max_m=6,
+                                max_n=24, operand_lo=-(1 << 12), operand_hi=1 << 12), w)
+    compare(run_gpu(ctx, b, 200), oracle.run(b, 200, w=w))
+
+
+def test_busy_beavers_halting_numbers_on_gpu(ctx, rasp):
+    """App. B's captions on the GPU: the three busy beavers halt after
+    exactly 1549, 1272 and 1255 transitions at w = 29, and the whole final
+    configurations equal the oracle's at w = 29 and w = 32."""
+    configure(ctx, rasp, "persistent-lds32")
+    with open(os.path.join(GOLDEN, "busy_beavers.json")) as f:
+        spec = json.load(f)
+    m = spec["machine"]
+    progs = []
+    for p in spec["programs"]:
+        with open(os.path.join(GOLDEN, p["file"])) as f:
+            pairs, _ = dsl.lower_word(dsl.parse(f.read()), ell=m["ell"], s=m["s"], mu=m["mu"])
+        progs.append(dsl.flatten(pairs))
+    for w in (29, 32):
+        b = W.from_programs(W.ISA_WORD, progs, m["n"], [[]] * 3, ell=m["ell"], s=m["s"])
+        b.word_bits = w
+        got = run_gpu(ctx, b, 10 ** 6)
+        compare(got, oracle.run(b, 10 ** 6, w=w))
+        assert (got["status"] == 1).all()
+        if w == 29:
+            assert got["steps"].tolist() == [p["tau_h"] for p in spec["programs"]]
+
+
+def test_narrow_words_reject_wide_values(ctx, rasp):
+    R = rasp
+    b = _to_width(W.config1(num_vms=16), 8)
+    b.prog = b.prog.copy()
+    b.prog[5] = 200                             # not an 8-bit word
+    with pytest.raises(R.RaspError) as e:
+        ctx.load(b)
+    assert e.value.code == R.RASP_E_INVAL
+    with pytest.raises(R.RaspError) as e:
+        R.rasp_load_batch(ctx.handle, R.make_desc(b, ctx.device))
+    assert e.value.code == R.RASP_E_INVAL
+    ok = _to_width(W.config1(num_vms=16), 8)
+    st = oracle.init(ok, w=8)
+    st.a = st.a.copy()
+    st.a[2] = 1000                              # a state word wider than 8 bits
+    with pytest.raises(R.RaspError) as e:
+        ctx.load_state(ok, dict(i=st.i, a=st.a, u0=st.u0, y0=st.y0, mem=st.mem))
+    assert e.value.code == R.RASP_E_INVAL
+    bad_w = W.config1(num_vms=4)
+    bad_w.word_bits = 33
+    with pytest.raises(R.RaspError) as e:
+        ctx.load(bad_w)
+    assert e.value.code == R.RASP_E_INVAL
+    compare(run_gpu(ctx, ok, 256), oracle.run(ok, 256, w=8))

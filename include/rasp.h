@@ -273,8 +273,8 @@ int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
  *                          first runs in a first pass; the machines still
  *                          running then go through the persistent kernel
  *                          (0: persistent kernel only)
- *   RASP_OPT_FIRST_PASS_KIND  0: the first pass is the plain kernel (memory
- *                          in HBM, one machine per lane); 1 (default): the
+ *   RASP_OPT_FIRST_PASS_KIND  0 (default): the first pass is the plain
+ *                          kernel (memory in HBM, one machine per lane); 1: the
  *                          persistent kernel with every machine's memory in
  *                          its LDS slot, when every memory fits a slot
  *                          (otherwise the plain kernel)

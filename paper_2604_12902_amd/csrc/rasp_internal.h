@@ -82,6 +82,7 @@ hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
                          const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
                          uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
                          uint64_t *n_pad, uint32_t *err, uint32_t *max_n, hipStream_t st);
+// (max_n[0] = max n, [1] = some n not a power of two, [2] = max l)
 hipError_t launch_scan_u64(const uint64_t *in, uint64_t *out_excl, uint64_t N,
                            uint64_t *block_sums, uint64_t *total, hipStream_t st);
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out_excl, uint64_t N,
@@ -108,10 +109,12 @@ hipError_t launch_check_words(const int32_t *w, uint64_t count, uint32_t wshift,
 // the same for words [off[0], off[N]) of w, the offsets in device memory
 hipError_t launch_check_words_off(const int32_t *w, const uint64_t *off, uint64_t N, uint32_t wshift,
                                   uint32_t *err, hipStream_t st);
-// LDS words of one lane's slot for a launch (memory words, spare word and,
-// when every machine's memory fits, its tape); 0 for memory in HBM
+// LDS words of one lane's slot for a launch (memory words, four spare words
+// and, when every memory fits and tapes are short, the tape); 0 for memory in HBM
 uint32_t slot_words(uint32_t lds_words, uint32_t max_n, uint32_t max_ell);
 constexpr uint32_t kTapeLdsMax = 64;     // tapes up to this many words are staged in LDS
+constexpr int kStageGroup = 8;           // machines staged into LDS per batch of loads
+constexpr int kWriteGroup = 8;           // machines written back per batch of LDS reads
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
 hipError_t launch_reset_head(QueueState *q, hipStream_t st);     // head = 0, counts kept
 void init_kernel_attributes();

@@ -140,6 +140,12 @@ struct TapeL {
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
 };
 
+// output words, appended in HBM
+struct OutG {
+    gi32 *Y;
+    __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const { if (en) Y[k] = v; }
+};
+
 // ---------------------------------------------------------------------------
 // the step loop
 // ---------------------------------------------------------------------------
@@ -180,10 +186,12 @@ __device__ __forceinline__ bool stuck(uint32_t op, int32_t j, int32_t a, int32_t
     return !valid | ((op == 6u) & (u0 >= ell)) | (taken & (j == i));
 }
 
-// WM: words narrower than 32 bits (ws = 32 - w; POW2 then also needs n <= 2^w)
-template <int ISA, bool POW2, bool WM, class Mem, class Tape>
+// WM: words narrower than 32 bits (ws = 32 - w; POW2 then also needs n <= 2^w).
+// A tape staged in LDS is read one step ahead: the word at u0 is loaded with
+// the next instruction's words, so a READ costs no extra round trip.
+template <int ISA, bool POW2, bool WM, class Mem, class Tape, class Out>
 __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape, Regs &r,
-                                                gi32 *__restrict__ Y,
+                                                const Out &out,
                                                 uint32_t limit, bool &halted, bool &wrote,
                                                 uint32_t ws)
 {
@@ -193,6 +201,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
     int32_t i = r.i, a = r.a;
     int32_t o = mem.ld(p);
     int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
+    int32_t tv = Tape::kLds ? tape.ld(u0 < ell ? u0 : 0u) : 0;
     uint32_t left = limit;
     uint32_t wr = 0;
     for (;;) {
@@ -240,8 +249,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         const bool st_en = (op == 4u) | rd_ok;
         int32_t w = a;
         if (Tape::kLds) {
-            const int32_t tv = tape.ld(u0 < ell ? u0 : 0u);    // staged: read unconditionally
-            w = rd_ok ? tv : a;
+            w = rd_ok ? tv : a;                                // loaded one step ahead
         } else if (rd_ok) {
             w = tape.ld(u0);
         }
@@ -253,6 +261,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         const int32_t jcur = j;
         o = mem.ld(np);
         j = mem.ld(nq);
+        if (Tape::kLds) tv = tape.ld(u0 < ell ? u0 : 0u);
 
         const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);
         uint32_t na = op == 3u ? (ISA == 1 ? ua - ud : ua * ud) : ua;
@@ -261,7 +270,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         na = op == 1u ? static_cast<uint32_t>(jcur) : na;
         a = static_cast<int32_t>(na);
         const bool app = (op == 7u) & (y0 < s);
-        if (app) Y[y0] = d;
+        out.st(y0, d, app);
         y0 += app ? 1u : 0u;
         i = ni;
         p = np;
@@ -373,7 +382,7 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     GlobalMem g{gptr(b.M + b.mem_off[v])};
     TapeG tg{gptr(b.T + b.t_off[v])};
     bool halted, wrote = false;
-    run_machine<ISA, false, true>(g, tg, r, gptr(b.Y + b.y_off[v]), 0u, halted, wrote, b.wshift);
+    run_machine<ISA, false, true>(g, tg, r, OutG{gptr(b.Y + b.y_off[v])}, 0u, halted, wrote, b.wshift);
     b.status[v] = halted ? 1 : 0;
 }
 
@@ -470,10 +479,9 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             GlobalMem m{gptr(b.M + b.mem_off[v])};
             TapeG tg{gptr(b.T + b.t_off[v])};
             bool halted, wrote = false;
-            const uint32_t t = wm ? run_machine<ISA, POW2, true>(m, tg, r, gptr(b.Y + b.y_off[v]), limit,
-                                                                 halted, wrote, b.wshift)
-                                  : run_machine<ISA, POW2, false>(m, tg, r, gptr(b.Y + b.y_off[v]), limit,
-                                                                  halted, wrote, 0u);
+            const OutG og{gptr(b.Y + b.y_off[v])};
+            const uint32_t t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, wrote, b.wshift)
+                                  : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, wrote, 0u);
             if (t || fresh) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
                 b.steps[v] = fresh ? t : b.steps[v] + t;
@@ -541,6 +549,9 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uin
 // With surv non-null the launch is a first pass: a machine runs at most `cap`
 // transitions, and one still running after them is written back and appended
 // to surv (its index in the launch) for a later launch.
+// TLDS (MODE 1 only): the tape (TL words) is staged in the slot too, after
+// the memory and four spare words (the first spare takes the stores that do
+// not happen).
 // ---------------------------------------------------------------------------
 
 // four words as one 16-byte access; global and LDS views of it
@@ -575,7 +586,8 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = threadIdx.x / kWave;
-    const uint32_t SP = P + 4u + (TLDS ? TL : 0u);         // slot: P words, spare, tape
+    const uint32_t TB = P + 4u;                            // tape offset in a slot
+    const uint32_t SP = P + 4u + (TLDS ? TL : 0u);         // slot: memory, spares, tape
     const uint32_t wave_base = wib * kWave * SP;           // word index of lane 0's slot
     const uint32_t slot = wave_base + lane * SP;
     if (work != nullptr) total = q->survivors;             // written by the first pass
@@ -664,10 +676,14 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             const uint32_t fr = (claimed && fresh) ? 1u : 0u;
             uint64_t cm = __ballot(claimed);
             while (cm) {
-                uint32_t Ls[4], C[4], SL[4], D[4], AL[4], nL = 0, Cmax = 0;
-                const int32_t *S[4];
+                // up to kStageGroup machines: every load of a row is issued
+                // before the row's LDS writes, so the group pays one memory
+                // latency per row of 256 words
+                uint32_t Ls[kStageGroup], C[kStageGroup], SL[kStageGroup], D[kStageGroup], AL[kStageGroup];
+                const int32_t *S[kStageGroup];
+                uint32_t nL = 0, Cmax = 0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kStageGroup; ++u) {
                     C[u] = 0; SL[u] = 0; D[u] = 0; AL[u] = 1; S[u] = nullptr; Ls[u] = 0;
                     if (cm) {
                         const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
@@ -684,35 +700,52 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                 }
                 for (uint32_t k0 = 0; k0 < Cmax; k0 += 4u * kWave) {
                     const uint32_t k = k0 + 4u * lane;
-                    v4i w[4];
+                    v4i w[kStageGroup];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < kStageGroup; ++u)
                         if (k < C[u]) w[u] = load4(S[u], k, SL[u], AL[u] != 0);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int u = 0; u < kStageGroup; ++u)
                         if (k < C[u]) *reinterpret_cast<v4i *>(&rasp_lds[D[u] + k]) = w[u];
                 }
-                // a new machine's tape x 0^(l-|x|) and output 0^s in HBM; the
-                // tape also into the slot when it is staged there
+                // tapes: a new machine's x 0^(l-|x|) and output 0^s in HBM; the
+                // tape also into the slot when it is staged there.  The first
+                // 64 words of every machine of the group are loaded before any
+                // is stored (global loads and stores may alias, so they would
+                // otherwise serialize machine by machine)
+                uint32_t EL[kStageGroup], TN[kStageGroup], SS[kStageGroup], F[kStageGroup];
+                const gi32 *TS[kStageGroup];
+                gi32 *TD[kStageGroup], *YD[kStageGroup];
+                int32_t xt[kStageGroup];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (static_cast<uint32_t>(u) >= nL) break;
-                    const uint32_t L = Ls[u];
-                    const bool F = bcast(fr, L) != 0;
-                    if (!F && !TLDS) continue;
-                    const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L);
-                    const gi32 *TS = gptr(reinterpret_cast<const int32_t *>(
-                        bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
-                    gi32 *TD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(T), L)));
-                    for (uint32_t e = lane; e < EL; e += kWave) {
-                        const int32_t x = e < TN ? TS[e] : 0;
-                        if (F) TD[e] = x;
-                        if (TLDS) rasp_lds[D[u] + P + 4u + e] = x;
+                for (int u = 0; u < kStageGroup; ++u) {
+                    EL[u] = 0; TN[u] = 0; SS[u] = 0; F[u] = 0; xt[u] = 0;
+                    TS[u] = nullptr; TD[u] = nullptr; YD[u] = nullptr;
+                    if (static_cast<uint32_t>(u) < nL) {
+                        const uint32_t L = Ls[u];
+                        F[u] = bcast(fr, L);
+                        if (F[u] || TLDS) {
+                            EL[u] = bcast(r.ell, L); TN[u] = bcast(tlen, L); SS[u] = bcast(r.s, L);
+                            TS[u] = gptr(reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
+                            TD[u] = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(T), L)));
+                            YD[u] = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Y), L)));
+                        }
                     }
-                    if (F) {
-                        const uint32_t SS = bcast(r.s, L);
-                        gi32 *YD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Y), L)));
-                        for (uint32_t e = lane; e < SS; e += kWave) YD[e] = 0;
+                }
+#pragma unroll
+                for (int u = 0; u < kStageGroup; ++u)
+                    if (lane < EL[u] && lane < TN[u]) xt[u] = TS[u][lane];
+#pragma unroll
+                for (int u = 0; u < kStageGroup; ++u) {
+                    if (lane < EL[u]) {
+                        if (F[u]) TD[u][lane] = xt[u];
+                        if (TLDS) rasp_lds[D[u] + TB + lane] = xt[u];
+                    }
+                    if (F[u]) {
+                        if (lane < SS[u]) YD[u][lane] = 0;
+                        // words beyond the first 64 (tapes not staged in LDS)
+                        for (uint32_t e = lane + kWave; e < EL[u]; e += kWave) TD[u][e] = e < TN[u] ? TS[u][e] : 0;
+                        for (uint32_t e = lane + kWave; e < SS[u]; e += kWave) YD[u][e] = 0;
                     }
                 }
             }
@@ -725,26 +758,30 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             bool halted;
             uint32_t t;
             // wm is uniform: one of the two loop bodies runs
-#define RASP_RUN(mm, tp)                                                                        \
-    (wm ? run_machine<ISA, POW2, true>(mm, tp, r, gptr(Y), lim, halted, wrote, ws)             \
-        : run_machine<ISA, POW2, false>(mm, tp, r, gptr(Y), lim, halted, wrote, 0u))
+#define RASP_RUN(mm, tp, ou)                                                                    \
+    (wm ? run_machine<ISA, POW2, true>(mm, tp, r, ou, lim, halted, wrote, ws)                  \
+        : run_machine<ISA, POW2, false>(mm, tp, r, ou, lim, halted, wrote, 0u))
             if (MODE == 1) {
                 LdsMem mm{slot, slot + P};
                 if (TLDS) {
-                    TapeL tl{slot + P + 4u};
-                    t = RASP_RUN(mm, tl);
+                    TapeL tl{slot + TB};
+                    OutG og{gptr(Y)};
+                    t = RASP_RUN(mm, tl, og);
                 } else {
                     TapeG tg{gptr(T)};
-                    t = RASP_RUN(mm, tg);
+                    OutG og{gptr(Y)};
+                    t = RASP_RUN(mm, tg, og);
                 }
             } else if (MODE == 2) {
                 SplitMem mm{slot, P, gptr(M)};
                 TapeG tg{gptr(T)};
-                t = RASP_RUN(mm, tg);
+                OutG og{gptr(Y)};
+                t = RASP_RUN(mm, tg, og);
             } else {
                 GlobalMem mm{gptr(M)};
                 TapeG tg{gptr(T)};
-                t = RASP_RUN(mm, tg);
+                OutG og{gptr(Y)};
+                t = RASP_RUN(mm, tg, og);
             }
 #undef RASP_RUN
             done += t;
@@ -763,12 +800,32 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             const uint32_t cnt = r.n < P ? r.n : P;
             uint64_t fm = __ballot(finish && (wrote || fresh));
             while (fm) {
-                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
-                fm &= fm - 1ull;
-                const uint32_t C = bcast(cnt, L), D = wave_base + L * SP;
-                gi32 *MD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L)));
-                for (uint32_t k = 4u * lane; k < C; k += 4u * kWave)
-                    *reinterpret_cast<gv4i *>(MD + k) = *reinterpret_cast<const v4i *>(&rasp_lds[D + k]);
+                // kWriteGroup machines: their LDS rows are read before any is stored
+                uint32_t C[kWriteGroup], D[kWriteGroup];
+                gi32 *MD[kWriteGroup];
+                uint32_t Cmax = 0;
+#pragma unroll
+                for (int u = 0; u < kWriteGroup; ++u) {
+                    C[u] = 0; D[u] = 0; MD[u] = nullptr;
+                    if (fm) {
+                        const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
+                        fm &= fm - 1ull;
+                        C[u] = bcast(cnt, L);
+                        D[u] = wave_base + L * SP;
+                        MD[u] = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L)));
+                        Cmax = C[u] > Cmax ? C[u] : Cmax;
+                    }
+                }
+                for (uint32_t k0 = 0; k0 < Cmax; k0 += 4u * kWave) {
+                    const uint32_t k = k0 + 4u * lane;
+                    v4i w[kWriteGroup];
+#pragma unroll
+                    for (int u = 0; u < kWriteGroup; ++u)
+                        if (k < C[u]) w[u] = *reinterpret_cast<const v4i *>(&rasp_lds[D[u] + k]);
+#pragma unroll
+                    for (int u = 0; u < kWriteGroup; ++u)
+                        if (k < C[u]) *reinterpret_cast<gv4i *>(MD[u] + k) = w[u];
+                }
             }
         }
         // ---- first pass: append the machines still running to the survivor list ----
@@ -790,8 +847,7 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
 template <int ISA, int MODE, bool POW2, bool TLDS>
 static hipError_t launch_k3(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const BatchTable *tab,
                             uint64_t total, const uint32_t *work, uint32_t already, uint32_t epoch,
-                            uint32_t P, uint32_t TL, uint32_t wm, uint32_t cap, uint32_t *surv,
-                            QueueState *q)
+                            uint32_t P, uint32_t TL, uint32_t wm, uint32_t cap, uint32_t *surv, QueueState *q)
 {
     k_persistent<ISA, MODE, POW2, TLDS><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, P, TL,
                                                                     wm, cap, surv, q);
@@ -821,18 +877,20 @@ void init_kernel_attributes()
 template <int ISA, int MODE, bool TLDS>
 static hipError_t launch_k3_p(bool pow2, dim3 grid, dim3 block, size_t shmem, hipStream_t st,
                               const BatchTable *tab, uint64_t total, const uint32_t *work,
-                              uint32_t already, uint32_t epoch, uint32_t P, uint32_t TL, uint32_t wm,
-                              uint32_t cap, uint32_t *surv, QueueState *q)
+                              uint32_t already, uint32_t epoch, uint32_t P, uint32_t TL,
+                              uint32_t wm, uint32_t cap, uint32_t *surv, QueueState *q)
 {
     return pow2 ? launch_k3<ISA, MODE, true, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q)
                 : launch_k3<ISA, MODE, false, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
 }
 
+// the tape is staged in LDS when every memory fits its slot and every tape
+// is at most kTapeLdsMax words; the region is at least one 16-byte group
 uint32_t slot_words(uint32_t lds_words, uint32_t max_n, uint32_t max_ell)
 {
     if (lds_words == 0) return 0;
-    const uint32_t tl = (max_n <= lds_words && max_ell <= kTapeLdsMax) ? ((max_ell + 3u) & ~3u) : 0u;
-    return lds_words + 4u + tl;
+    const bool tl = max_n <= lds_words && max_ell <= kTapeLdsMax;
+    return lds_words + 4u + (tl ? ((max_ell < 1u ? 1u : max_ell) + 3u) & ~3u : 0u);
 }
 
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,

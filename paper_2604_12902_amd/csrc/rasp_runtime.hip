@@ -152,7 +152,7 @@ struct rasp_ctx {
     // options
     int64_t schedule = RASP_SCHED_AUTO, epoch = 256, lds_words = -1, waves_per_cu = 16, graph = 0;
     int64_t first_pass = 64;
-    int64_t first_pass_kind = 1;         // 1: LDS-resident first pass when memories fit
+    int64_t first_pass_kind = 0;         // 1: LDS-resident first pass when memories fit
     // scratch: queue counters, batch tables (device ring + pinned host ring)
     Alloc scratch;
     QueueState *queue = nullptr;
@@ -1266,7 +1266,8 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         *x = Batch();
         x->N = K;
         x->sum_n_pad = m_end; x->sum_ell = t_end; x->sum_s = y_end;
-        x->max_n = b->max_n; x->max_ell = b->max_ell; x->all_pow2 = b->all_pow2; x->status_stale = b->status_stale;
+        x->max_n = b->max_n; x->max_ell = b->max_ell; x->all_pow2 = b->all_pow2;
+        x->status_stale = b->status_stale;
         x->wbits = b->wbits;
         if (!arena_alloc(c, meta_bytes(K), &x->meta) || !arena_alloc(c, words_bytes(m_end, t_end, y_end), &x->words)) {
             arena_free(c, &snap.meta); arena_free(c, &snap.words);
@@ -1350,27 +1351,37 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         c->schedule = o[0]; c->lds_words = o[1]; c->first_pass = o[2]; c->epoch = o[3]; c->waves_per_cu = o[4];
         c->first_pass_kind = o[5];
     };
+    // one coordinate search (LDS words, first-pass length, epoch, waves per
+    // CU) for each first-pass kind, from the same start; the kinds interact
+    // with every other knob, so they are not searched one after the other
+    const int64_t start[6] = {cur[0], cur[1], cur[2], cur[3], cur[4], cur[5]};
+    const std::vector<int64_t> *lists[5] = {nullptr, &lds_c, &fp_c, &ep_c, &wv_c};
     double best = 1e30;
-    apply(cur);
-    rc = trial_ms(&best);
-    // warm-up run above; measure the starting point again
-    if (!rc) rc = trial_ms(&best);
-    const std::vector<int64_t> *lists[6] = {nullptr, &lds_c, &fp_c, &ep_c, &wv_c, &fk_c};
-    // the first-pass kind first: it changes which lengths and epochs pay
-    const int order[] = {1, 5, 2, 3, 4};
-    for (int oi = 0; oi < 5 && !rc; ++oi) {
-        const int knob = order[oi];
-        for (int64_t val : *lists[knob]) {
-            if (val == cur[knob]) continue;
-            if (knob == 1 && val > 0 &&
-                static_cast<uint64_t>(kWave) * slot_words(static_cast<uint32_t>(val), b->max_n, b->max_ell) * 4 >
-                    static_cast<uint64_t>(c->lds_bytes)) continue;
-            int64_t o[6] = {cur[0], cur[1], cur[2], cur[3], cur[4], cur[5]};
-            o[knob] = val;
-            apply(o);
-            double ms = 0;
-            if ((rc = trial_ms(&ms))) break;
-            if (ms < best) { best = ms; cur[knob] = val; }
+    bool warm = false;
+    for (int64_t kind : fk_c) {
+        if (rc) break;
+        int64_t kc[6] = {start[0], start[1], start[2], start[3], start[4], kind};
+        double kbest = 1e30;
+        apply(kc);
+        if (!warm) { rc = trial_ms(&kbest); warm = true; }     // warm-up run
+        if (!rc) rc = trial_ms(&kbest);
+        for (int knob = 1; knob <= 4 && !rc; ++knob) {
+            for (int64_t val : *lists[knob]) {
+                if (val == kc[knob]) continue;
+                if (knob == 1 && val > 0 &&
+                    static_cast<uint64_t>(kWave) * slot_words(static_cast<uint32_t>(val), b->max_n, b->max_ell) * 4 >
+                        static_cast<uint64_t>(c->lds_bytes)) continue;
+                int64_t o[6] = {kc[0], kc[1], kc[2], kc[3], kc[4], kc[5]};
+                o[knob] = val;
+                apply(o);
+                double ms = 0;
+                if ((rc = trial_ms(&ms))) break;
+                if (ms < kbest) { kbest = ms; kc[knob] = val; }
+            }
+        }
+        if (!rc && kbest < best) {
+            best = kbest;
+            for (int q = 0; q < 6; ++q) cur[q] = kc[q];
         }
     }
     if (!rc) {                              // the plain schedule as a whole

@@ -397,7 +397,7 @@ def test_autotune_leaves_the_batch_and_stays_bit_exact(ctx, rasp):
     ctx.set(R.RASP_OPT_FIRST_PASS, 64)
     ctx.set(R.RASP_OPT_EPOCH, 256)
     ctx.set(R.RASP_OPT_WAVES_PER_CU, 16)
-    ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 1)
+    ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 0)
 
 
 def test_autotune_on_a_lazy_batch(ctx, rasp):
@@ -419,7 +419,7 @@ def test_autotune_on_a_lazy_batch(ctx, rasp):
         ctx.set(R.RASP_OPT_FIRST_PASS, 64)
         ctx.set(R.RASP_OPT_EPOCH, 256)
         ctx.set(R.RASP_OPT_WAVES_PER_CU, 16)
-        ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 1)
+        ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 0)
 
 
 @pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "firstpass-lds64", "ldsfirst-lds64"])

@@ -557,32 +557,28 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uin
 // four words as one 16-byte access; global and LDS views of it
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) v4i gv4i;
-
-// 16 bytes of global memory at word k of S (S 16-byte aligned when al), with
-// words at or beyond len read as zero
-__device__ __forceinline__ v4i load4(const int32_t *S, uint32_t k, uint32_t len, bool al)
+// direct global-to-LDS loads: lane l's 4 (or 16) bytes from g land at LDS
+// word row + l (or row + 4 l); row is the same for every lane of the wave
+typedef __attribute__((address_space(1))) void gv;
+typedef __attribute__((address_space(3))) void lv;
+__device__ __forceinline__ void dma4(const int32_t *g, uint32_t row)
 {
-    const gi32 *G = gptr(S);
-    v4i w;
-    if (al && k + 4u <= len) {
-        w = *reinterpret_cast<const gv4i *>(G + k);
-    } else {
-        w.x = k < len ? G[k] : 0;
-        w.y = k + 1u < len ? G[k + 1u] : 0;
-        w.z = k + 2u < len ? G[k + 2u] : 0;
-        w.w = k + 3u < len ? G[k + 3u] : 0;
-    }
-    return w;
+    __builtin_amdgcn_global_load_lds((const gv *)g, (lv *)&rasp_lds[row], 4, 0, 0);
+}
+__device__ __forceinline__ void dma16(const int32_t *g, uint32_t row)
+{
+    __builtin_amdgcn_global_load_lds((const gv *)g, (lv *)&rasp_lds[row], 16, 0, 0);
 }
 
-template <int ISA, int MODE, bool POW2, bool TLDS>
-__global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict__ tab,
-                                                    uint64_t total,
-                                                    const uint32_t *__restrict__ work,
-                                                    uint32_t already, uint32_t epoch,
-                                                    uint32_t P, uint32_t TL, uint32_t wm,
-                                                    uint32_t cap, uint32_t *__restrict__ surv,
-                                                    QueueState *__restrict__ q)
+// ONE: the launch holds a single batch, so every lane's batch is tab->b[0]
+// and its fields are wave-uniform (scalar loads, kept across refills); a
+// refill then waits on one round of per-machine loads
+template <int ISA, int MODE, bool POW2, bool TLDS, bool ONE>
+__device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ tab, uint64_t total,
+                                                const uint32_t *__restrict__ work, uint32_t already,
+                                                uint32_t epoch, uint32_t P, uint32_t TL, uint32_t wm,
+                                                uint32_t cap, uint32_t *__restrict__ surv,
+                                                QueueState *__restrict__ q)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = threadIdx.x / kWave;
@@ -618,9 +614,9 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                 const uint64_t item = base + __popcll(idle & ((1ull << lane) - 1ull));
                 if (item < total) {
                     const uint64_t g = work ? static_cast<uint64_t>(work[item]) : item;
-                    const int k = batch_of(tab, g);
+                    const int k = ONE ? 0 : batch_of(tab, g);
                     bp = &tab->b[k];
-                    v = g - tab->start[k];
+                    v = ONE ? g : g - tab->start[k];
                     const uint32_t budget = tab->budget[k];
                     fresh = bp->fresh != 0;
                     if ((fresh || bp->status[v] == 0) && budget > already) {
@@ -652,6 +648,11 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
             continue;
         }
         // ---- stage the claimed machines' low memory words into their slots ----
+        // Direct global-to-LDS loads: each lane's 16 (or 4) bytes land at the
+        // row's LDS base + 16 (or 4) x lane, so one instruction moves a 256-word
+        // row (64 words for a program not 16-byte aligned) without passing
+        // through registers.  Every claimed machine's rows are issued before a
+        // single wait, so a refill pays about one memory latency.
         if (MODE != 0) {
             // what each claiming lane's copy reads: the packed program (c0 of a
             // new machine, Sec. 2.1: program words, then zeros) or its memory
@@ -663,7 +664,7 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                     const uint64_t p0 = bp->prog_off[v], t0 = bp->tape_off[v];
                     src = bp->prog + p0;
                     srclen = static_cast<uint32_t>(bp->prog_off[v + 1] - p0);
-                    al = (p0 & 3u) == 0 ? 1u : 0u;
+                    al = ((reinterpret_cast<uintptr_t>(src) & 15u) == 0 && (srclen & 3u) == 0) ? 1u : 0u;
                     tsrc = bp->tape + t0;
                     tlen = static_cast<uint32_t>(bp->tape_off[v + 1] - t0);
                 } else {
@@ -674,80 +675,64 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                 }
             }
             const uint32_t fr = (claimed && fresh) ? 1u : 0u;
-            uint64_t cm = __ballot(claimed);
+            const uint64_t claimed_mask = __ballot(claimed);
+            // plain LDS stores first (the zeros after a new machine's program
+            // and tape): issued after a direct load they would wait for it
+            uint64_t cm = claimed_mask;
             while (cm) {
-                // up to kStageGroup machines: every load of a row is issued
-                // before the row's LDS writes, so the group pays one memory
-                // latency per row of 256 words
-                uint32_t Ls[kStageGroup], C[kStageGroup], SL[kStageGroup], D[kStageGroup], AL[kStageGroup];
-                const int32_t *S[kStageGroup];
-                uint32_t nL = 0, Cmax = 0;
-#pragma unroll
-                for (int u = 0; u < kStageGroup; ++u) {
-                    C[u] = 0; SL[u] = 0; D[u] = 0; AL[u] = 1; S[u] = nullptr; Ls[u] = 0;
-                    if (cm) {
-                        const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
-                        cm &= cm - 1ull;
-                        Ls[u] = L;
-                        C[u] = bcast(cnt, L);
-                        SL[u] = bcast(srclen, L);
-                        AL[u] = bcast(al, L);
-                        S[u] = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(src), L));
-                        D[u] = wave_base + L * SP;
-                        Cmax = C[u] > Cmax ? C[u] : Cmax;
-                        nL = u + 1;
-                    }
+                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
+                cm &= cm - 1ull;
+                const uint32_t C = bcast(cnt, L), SL = bcast(srclen, L), D = wave_base + L * SP;
+                const uint32_t n4 = SL < C ? SL : C;            // words copied from the source
+                // up to the next 16 bytes one word a lane, then 16 bytes a lane
+                const uint32_t z4 = (n4 + 3u) & ~3u;
+                if (lane < z4 - n4 && n4 + lane < C) rasp_lds[D + n4 + lane] = 0;
+                for (uint32_t k = z4 + 4u * lane; k < C; k += 4u * kWave)
+                    *reinterpret_cast<v4i *>(&rasp_lds[D + k]) = v4i{0, 0, 0, 0};
+                if (TLDS) {
+                    const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L);
+                    if (lane < EL && lane >= TN) rasp_lds[D + TB + lane] = 0;
                 }
-                for (uint32_t k0 = 0; k0 < Cmax; k0 += 4u * kWave) {
-                    const uint32_t k = k0 + 4u * lane;
-                    v4i w[kStageGroup];
-#pragma unroll
-                    for (int u = 0; u < kStageGroup; ++u)
-                        if (k < C[u]) w[u] = load4(S[u], k, SL[u], AL[u] != 0);
-#pragma unroll
-                    for (int u = 0; u < kStageGroup; ++u)
-                        if (k < C[u]) *reinterpret_cast<v4i *>(&rasp_lds[D[u] + k]) = w[u];
+            }
+            // then every direct load: the memory (or program) rows and the tape
+            cm = claimed_mask;
+            while (cm) {
+                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
+                cm &= cm - 1ull;
+                const uint32_t C = bcast(cnt, L), SL = bcast(srclen, L), D = wave_base + L * SP;
+                const uint32_t n4 = SL < C ? SL : C;
+                const int32_t *S = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(src), L));
+                if (bcast(al, L)) {
+                    for (uint32_t k0 = 0; k0 < n4; k0 += 4u * kWave)
+                        if (k0 + 4u * lane < n4) dma16(S + k0 + 4u * lane, D + k0);
+                } else {
+                    for (uint32_t k0 = 0; k0 < n4; k0 += kWave)
+                        if (k0 + lane < n4) dma4(S + k0 + lane, D + k0);
                 }
-                // tapes: a new machine's x 0^(l-|x|) and output 0^s in HBM; the
-                // tape also into the slot when it is staged there.  The first
-                // 64 words of every machine of the group are loaded before any
-                // is stored (global loads and stores may alias, so they would
-                // otherwise serialize machine by machine)
-                uint32_t EL[kStageGroup], TN[kStageGroup], SS[kStageGroup], F[kStageGroup];
-                const gi32 *TS[kStageGroup];
-                gi32 *TD[kStageGroup], *YD[kStageGroup];
-                int32_t xt[kStageGroup];
-#pragma unroll
-                for (int u = 0; u < kStageGroup; ++u) {
-                    EL[u] = 0; TN[u] = 0; SS[u] = 0; F[u] = 0; xt[u] = 0;
-                    TS[u] = nullptr; TD[u] = nullptr; YD[u] = nullptr;
-                    if (static_cast<uint32_t>(u) < nL) {
-                        const uint32_t L = Ls[u];
-                        F[u] = bcast(fr, L);
-                        if (F[u] || TLDS) {
-                            EL[u] = bcast(r.ell, L); TN[u] = bcast(tlen, L); SS[u] = bcast(r.s, L);
-                            TS[u] = gptr(reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
-                            TD[u] = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(T), L)));
-                            YD[u] = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Y), L)));
-                        }
-                    }
+                if (TLDS) {                                     // tape x 0^(l-|x|) into the slot
+                    const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L);
+                    const int32_t *TS = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L));
+                    if (lane < EL && lane < TN) dma4(TS + lane, D + TB);
                 }
-#pragma unroll
-                for (int u = 0; u < kStageGroup; ++u)
-                    if (lane < EL[u] && lane < TN[u]) xt[u] = TS[u][lane];
-#pragma unroll
-                for (int u = 0; u < kStageGroup; ++u) {
-                    if (lane < EL[u]) {
-                        if (F[u]) TD[u][lane] = xt[u];
-                        if (TLDS) rasp_lds[D[u] + TB + lane] = xt[u];
-                    }
-                    if (F[u]) {
-                        if (lane < SS[u]) YD[u][lane] = 0;
-                        // words beyond the first 64 (tapes not staged in LDS)
-                        for (uint32_t e = lane + kWave; e < EL[u]; e += kWave) TD[u][e] = e < TN[u] ? TS[u][e] : 0;
-                        for (uint32_t e = lane + kWave; e < SS[u]; e += kWave) YD[u][e] = 0;
-                    }
+            }
+            if (claimed_mask) __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed
+            // a new machine's tape and output in HBM: x 0^(l-|x|) (from the
+            // slot when staged there) and 0^s
+            uint64_t fm = __ballot(fr != 0);
+            while (fm) {
+                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
+                fm &= fm - 1ull;
+                const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L), SS = bcast(r.s, L);
+                const uint32_t D = wave_base + L * SP;
+                gi32 *TD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(T), L)));
+                gi32 *YD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Y), L)));
+                if (TLDS) {
+                    if (lane < EL) TD[lane] = rasp_lds[D + TB + lane];
+                } else {
+                    const gi32 *TS = gptr(reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
+                    for (uint32_t e = lane; e < EL; e += kWave) TD[e] = e < TN ? TS[e] : 0;
                 }
+                for (uint32_t e = lane; e < SS; e += kWave) YD[e] = 0;
             }
         }
         // ---- run ----
@@ -842,6 +827,21 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
         }
         if (finish) has = false;
     }
+}
+
+template <int ISA, int MODE, bool POW2, bool TLDS>
+__global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict__ tab,
+                                                    uint64_t total,
+                                                    const uint32_t *__restrict__ work,
+                                                    uint32_t already, uint32_t epoch,
+                                                    uint32_t P, uint32_t TL, uint32_t wm,
+                                                    uint32_t cap, uint32_t *__restrict__ surv,
+                                                    QueueState *__restrict__ q)
+{
+    if (tab->count == 1)
+        persistent_body<ISA, MODE, POW2, TLDS, true>(tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+    else
+        persistent_body<ISA, MODE, POW2, TLDS, false>(tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
 }
 
 template <int ISA, int MODE, bool POW2, bool TLDS>

@@ -171,25 +171,13 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def kernels_source_sha() -> str:
-    import hashlib
-    path = os.path.join(ROOT, "paper_2604_12902_amd", "csrc", "rasp_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
-
-
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, knobs: dict):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or
-    None when there is none or the kernels have changed since."""
-    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel))
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        t = json.load(f)
-    if t.get("kernels_sha256") != kernels_source_sha():
-        return None
-    return t.get("bytes_per_launch")
+    summary (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size)
+    for a run with these knobs, or None when there is none or the kernels have
+    changed since."""
+    from paper_2604_12902_amd import counters
+    return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs)
 
 
 def main():
@@ -325,12 +313,16 @@ def main():
         if name == "plain" and args.no_plain:
             continue
         wall, per, kt = timed(sched)
+        knobs = dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
+                     first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
+                     waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
+                     first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=not args.eager)
         if args.verify != "none":
             verify()
         ms = 1e3 * wall / args.steps
         results[name] = dict(ms_per_step=ms, value=total_steps / (wall / args.steps),
                              p50_ms=float(np.percentile(per, 50) * 1e3),
-                             p99_ms=float(np.percentile(per, 99) * 1e3), kernels=kt)
+                             p99_ms=float(np.percentile(per, 99) * 1e3), kernels=kt, knobs=knobs)
         print("bench: %-10s %.3f ms/step  %.3e steps/s  p50 %.3f p99 %.3f ms  kernels %s" % (
             name, ms, results[name]["value"], results[name]["p50_ms"], results[name]["p99_ms"],
             {k: "%.3f ms x%d" % (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1]}),
@@ -341,7 +333,7 @@ def main():
     # dominant kernel of the headline schedule: largest total time
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
     dom_ms = kt[dom][0] / kt[dom][1]
-    fp_pass = int(ctx.get(R.RASP_OPT_FIRST_PASS))
+    fp_pass = head["knobs"]["first_pass"]
     # which launch built c0: the pack kernel, the first pass (plain or LDS
     # persistent kernel) or the persistent kernel itself
     first_kind = "first" if kt["first"][1] else ("plain" if kt["plain"][1] else None)
@@ -370,7 +362,7 @@ def main():
         algo = 0.0
         unit_note = "n/a"
     achieved = algo / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, dom)
+    traffic = measured_traffic(args.workload, dom, head["knobs"])
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
             "kernel": dom, "kernel_ms": round(dom_ms, 4), "algorithmic_bytes": int(algo),
@@ -391,11 +383,10 @@ def main():
         "data": "synthetic (seeded random RASP programs)",
         "config": {"workload": batch.name, "num_vms": N, "budget": budget,
                    "retired_steps_per_batch": total_steps, "schedule": "persistent",
-                   "first_pass": fp_pass, "lds_words": int(ctx.get(R.RASP_OPT_LDS_WORDS)),
+                   "first_pass": fp_pass, "lds_words": head["knobs"]["lds_words"],
                    "c0_in_run": not args.eager, "autotuned": tuned is not None,
-                   "epoch": int(ctx.get(R.RASP_OPT_EPOCH)),
-                   "waves_per_cu": int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
-                   "first_pass_kind": int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND))},
+                   "epoch": head["knobs"]["epoch"], "waves_per_cu": head["knobs"]["waves_per_cu"],
+                   "first_pass_kind": head["knobs"]["first_pass_kind"]},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "plain": ({k: results["plain"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms")}
                   if "plain" in results else None),

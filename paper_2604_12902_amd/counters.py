@@ -1,12 +1,17 @@
-"""Turn two rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE) of
-`bench.py --calibrate-copy BYTES ...` into HBM bytes per launch of a kernel.
+"""HBM bytes per launch of a kernel from two rocprofv3 counter runs.
 
-Both counters are read per dispatch in KiB.  The run's largest plain
-device-to-device copy (`__amd_rocclr_copyBuffer`, BYTES read and BYTES
-written) calibrates each counter: scale = BYTES / (counter KiB * 1024).  The
-kernel's mean counter value per dispatch times that scale is the traffic.
+The two runs (FETCH_SIZE, then WRITE_SIZE, each in KiB per dispatch) profile
+`bench.py --calibrate-copy BYTES ...`.  The run's largest plain device-to-device
+copy (`__amd_rocclr_copyBuffer`, BYTES read and BYTES written) calibrates each
+counter: scale = BYTES / (counter KiB * 1024).  A kernel's mean counter value
+per dispatch times that scale is its traffic.
 
-usage: python -m paper_2604_12902_amd.counters FETCH_DIR WRITE_DIR BYTES KERNEL_SUBSTRING OUT_JSON
+The result is recorded in profiles/<workload>_<kernel>_traffic.json under the
+scheduling knobs of the profiled run (the traffic of a launch depends on
+them) together with the SHA-256 of the kernel source; bench.py reports it
+only for a run with the same knobs and the same kernels.
+
+usage: python -m paper_2604_12902_amd.counters FETCH_DIR WRITE_DIR BYTES KERNEL_SUBSTRING OUT_JSON KNOBS_JSON
 """
 import glob
 import hashlib
@@ -14,6 +19,13 @@ import json
 import os
 import sqlite3
 import sys
+
+KERNELS_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "rasp_kernels.hip")
+
+
+def kernels_sha256() -> str:
+    with open(KERNELS_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def per_dispatch(d, counter):
@@ -28,8 +40,7 @@ def per_dispatch(d, counter):
     return out
 
 
-def main():
-    fdir, wdir, nbytes, ksub, out = sys.argv[1], sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5]
+def measure(fdir, wdir, nbytes, ksub):
     res = {"copy_bytes": nbytes, "kernel": ksub}
     for tag, d, c in (("fetch", fdir, "FETCH_SIZE"), ("write", wdir, "WRITE_SIZE")):
         vals = per_dispatch(d, c)
@@ -43,10 +54,38 @@ def main():
         res[tag + "_kernel_dispatches"] = len(kern)
         res[tag + "_bytes_per_launch"] = sum(kern) / len(kern) * 1024.0 * scale
     res["bytes_per_launch"] = res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"]
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "rasp_kernels.hip")
-    res["kernels_sha256"] = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return res
+
+
+def lookup(path, knobs):
+    """Bytes per launch recorded for these knobs and the current kernels, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernels_sha256") != kernels_sha256():
+        return None
+    for run in t.get("runs", []):
+        if run.get("knobs") == knobs:
+            return run["bytes_per_launch"]
+    return None
+
+
+def main():
+    fdir, wdir, nbytes, ksub, out = sys.argv[1], sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5]
+    knobs = json.loads(sys.argv[6])
+    res = measure(fdir, wdir, nbytes, ksub)
+    res["knobs"] = knobs
+    sha = kernels_sha256()
+    t = {"kernels_sha256": sha, "runs": []}
+    if os.path.exists(out):
+        with open(out) as f:
+            old = json.load(f)
+        if old.get("kernels_sha256") == sha:
+            t["runs"] = [r for r in old.get("runs", []) if r.get("knobs") != knobs]
+    t["runs"].append(res)
     with open(out, "w") as f:
-        json.dump(res, f, indent=1)
+        json.dump(t, f, indent=1)
     print(json.dumps(res, indent=1))
 
 

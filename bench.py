@@ -57,8 +57,8 @@ def parse():
     ap.add_argument("--lds-words", type=int, default=None)
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
-    ap.add_argument("--eager", action="store_true",
-                    help="build c0 in rasp_load_batch instead of inside the run (RASP_DESC_LAZY)")
+    ap.add_argument("--lazy", action="store_true",
+                    help="build c0 inside the run (RASP_DESC_LAZY) instead of in rasp_load_batch")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default knobs instead of running rasp_autotune")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -215,9 +215,9 @@ def main():
         cores, cpu_s, total_steps, bstep), flush=True)
 
     dev = torch.device("cuda", 0)
-    # inputs resident in HBM; by default c0 is built inside the run (the first
-    # plain pass packs each wave's machines before stepping them)
-    desc = R.make_desc(batch, dev, lazy=not args.eager)
+    # inputs resident in HBM; c0 is packed by rasp_load_batch (with --lazy the
+    # first launch of the run builds it)
+    desc = R.make_desc(batch, dev, lazy=args.lazy)
     N = batch.N
     outs = dict(status=torch.empty(N, dtype=torch.uint8, device=dev),
                 steps=torch.empty(N, dtype=torch.int64, device=dev),
@@ -234,9 +234,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     fp = R.rasp_batch_footprint(desc)
-    tune_vms = min(N, 1 << 18)
-    # the batch, its autotune snapshot and trial copy of a prefix, and slack
-    arena = int(fp * (1.25 + 2.0 * tune_vms / N)) + (256 << 20)
+    # tune on the whole batch (up to 4M machines): occupancy effects only show
+    # at the batch's real size
+    tune_vms = min(N, 1 << 22)
+    # the batch, its autotune snapshot and trial copy of a prefix, room to
+    # stage a dense memory dump for the verification fetch, and slack
+    arena = int(fp * (2.25 + 2.0 * tune_vms / N)) + (256 << 20)
     ctx = R.Context(arena)
     torch.cuda.synchronize()
 
@@ -316,7 +319,7 @@ def main():
         knobs = dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
                      first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
                      waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
-                     first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=not args.eager)
+                     first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=args.lazy)
         if args.verify != "none":
             verify()
         ms = 1e3 * wall / args.steps
@@ -384,7 +387,7 @@ def main():
         "config": {"workload": batch.name, "num_vms": N, "budget": budget,
                    "retired_steps_per_batch": total_steps, "schedule": "persistent",
                    "first_pass": fp_pass, "lds_words": head["knobs"]["lds_words"],
-                   "c0_in_run": not args.eager, "autotuned": tuned is not None,
+                   "c0_in_run": args.lazy, "autotuned": tuned is not None,
                    "epoch": head["knobs"]["epoch"], "waves_per_cu": head["knobs"]["waves_per_cu"],
                    "first_pass_kind": head["knobs"]["first_pass_kind"]},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],

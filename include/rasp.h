@@ -320,7 +320,8 @@ int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
  * first-pass length, epoch, waves per compute unit, first-pass kind;
  * persistent schedule against plain), keeps the fastest setting in the
  * context and writes it to chosen[0..5] = {schedule, lds_words, first_pass,
- * epoch, waves_per_cu, first_pass_kind} (chosen may be NULL).  Returns the
+ * epoch, waves_per_cu, first_pass_kind} (chosen may be NULL); a knob leaves
+ * its current setting only for a setting at least 3% faster.  Returns the
  * best time in *best_ms (may be NULL).  A lazily loaded batch stays lazy:
  * each trial builds c0 of the prefix again from the descriptor.
  * Errors: STATE, NOMEM (no room for the snapshot), DEVICE.

@@ -1233,6 +1233,10 @@ int rasp_kernel_times(rasp_ctx *c, double *ms, uint64_t *launches)
     return RASP_OK;
 }
 
+// a knob moves away from the current setting only for a trial at least 3%
+// faster: timings of near-equal settings differ by noise from run to run
+constexpr double kTuneMargin = 0.97;
+
 int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, int64_t *chosen,
                   double *best_ms)
 {
@@ -1376,10 +1380,10 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
                 apply(o);
                 double ms = 0;
                 if ((rc = trial_ms(&ms))) break;
-                if (ms < kbest) { kbest = ms; kc[knob] = val; }
+                if (ms < kbest * kTuneMargin) { kbest = ms; kc[knob] = val; }
             }
         }
-        if (!rc && kbest < best) {
+        if (!rc && kbest < best * kTuneMargin) {
             best = kbest;
             for (int q = 0; q < 6; ++q) cur[q] = kc[q];
         }
@@ -1389,7 +1393,7 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         apply(o);
         double ms = 0;
         rc = trial_ms(&ms);
-        if (!rc && ms < best) { best = ms; cur[0] = RASP_SCHED_PLAIN; }
+        if (!rc && ms < best * kTuneMargin) { best = ms; cur[0] = RASP_SCHED_PLAIN; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -159,7 +159,6 @@ struct Regs {
 
 // Advance one machine by at most `limit` transitions.  Returns the number
 // applied; `halted` says whether the machine now sits on a fixed point;
-// `wrote` is set when a transition stored into memory.
 //
 // Software-pipelined: the words of the next instruction are loaded together
 // with the data word of the current one (after the current store, so that a
@@ -192,7 +191,7 @@ __device__ __forceinline__ bool stuck(uint32_t op, int32_t j, int32_t a, int32_t
 template <int ISA, bool POW2, bool WM, class Mem, class Tape, class Out>
 __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape, Regs &r,
                                                 const Out &out,
-                                                uint32_t limit, bool &halted, bool &wrote,
+                                                uint32_t limit, bool &halted,
                                                 uint32_t ws)
 {
     const uint32_t n = r.n, nm = r.n - 1u, ell = r.ell, s = r.s;
@@ -201,9 +200,8 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
     int32_t i = r.i, a = r.a;
     int32_t o = mem.ld(p);
     int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
-    int32_t tv = Tape::kLds ? tape.ld(u0 < ell ? u0 : 0u) : 0;
+    int32_t tv = Tape::kLds ? tape.ld(u0) : 0;          // u0 <= l: the region has l + 1 words
     uint32_t left = limit;
-    uint32_t wr = 0;
     for (;;) {
         const uint32_t op = static_cast<uint32_t>(o);
         const bool is_rd = op == 6u;
@@ -254,14 +252,13 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             w = tape.ld(u0);
         }
         mem.st(jj, w, st_en);
-        wr |= st_en ? 1u : 0u;
         u0 += rd_ok ? 1u : 0u;
         const bool need = (op == 2u) | (op == 3u) | (op == 7u);
         const int32_t d = mem.ld_data(jj, need);
         const int32_t jcur = j;
         o = mem.ld(np);
         j = mem.ld(nq);
-        if (Tape::kLds) tv = tape.ld(u0 < ell ? u0 : 0u);
+        if (Tape::kLds) tv = tape.ld(u0);
 
         const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);
         uint32_t na = op == 3u ? (ISA == 1 ? ua - ud : ua * ud) : ua;
@@ -277,7 +274,6 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         --left;
     }
     halted = stuck<ISA>(static_cast<uint32_t>(o), j, a, i, u0, ell);
-    wrote |= wr != 0u;
     r.i = i; r.a = a; r.p = p; r.u0 = u0; r.y0 = y0;
     return limit - left;
 }
@@ -381,8 +377,8 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     r.p = cmod(r.i, r.n);
     GlobalMem g{gptr(b.M + b.mem_off[v])};
     TapeG tg{gptr(b.T + b.t_off[v])};
-    bool halted, wrote = false;
-    run_machine<ISA, false, true>(g, tg, r, OutG{gptr(b.Y + b.y_off[v])}, 0u, halted, wrote, b.wshift);
+    bool halted;
+    run_machine<ISA, false, true>(g, tg, r, OutG{gptr(b.Y + b.y_off[v])}, 0u, halted, b.wshift);
     b.status[v] = halted ? 1 : 0;
 }
 
@@ -478,10 +474,10 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             const uint32_t limit = cap < budget ? cap : budget;
             GlobalMem m{gptr(b.M + b.mem_off[v])};
             TapeG tg{gptr(b.T + b.t_off[v])};
-            bool halted, wrote = false;
+            bool halted;
             const OutG og{gptr(b.Y + b.y_off[v])};
-            const uint32_t t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, wrote, b.wshift)
-                                  : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, wrote, 0u);
+            const uint32_t t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, b.wshift)
+                                  : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, 0u);
             if (t || fresh) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
                 b.steps[v] = fresh ? t : b.steps[v] + t;
@@ -588,7 +584,7 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
     const uint32_t slot = wave_base + lane * SP;
     if (work != nullptr) total = q->survivors;             // written by the first pass
 
-    bool has = false, exhausted = false, wrote = false, fresh = false, cut = false;
+    bool has = false, exhausted = false, fresh = false, cut = false;
     Regs r{};
     int32_t *M = nullptr;
     int32_t *T = nullptr;
@@ -636,7 +632,6 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
                         limit = budget - already;
                         cut = cap < limit;
                         if (cut) limit = cap;
-                        wrote = false;
                         has = true;
                         claimed = true;
                     }
@@ -744,8 +739,8 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
             uint32_t t;
             // wm is uniform: one of the two loop bodies runs
 #define RASP_RUN(mm, tp, ou)                                                                    \
-    (wm ? run_machine<ISA, POW2, true>(mm, tp, r, ou, lim, halted, wrote, ws)                  \
-        : run_machine<ISA, POW2, false>(mm, tp, r, ou, lim, halted, wrote, 0u))
+    (wm ? run_machine<ISA, POW2, true>(mm, tp, r, ou, lim, halted, ws)                         \
+        : run_machine<ISA, POW2, false>(mm, tp, r, ou, lim, halted, 0u))
             if (MODE == 1) {
                 LdsMem mm{slot, slot + P};
                 if (TLDS) {
@@ -780,10 +775,11 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
                 survive = cut && !halted;
             }
         }
-        // ---- write back the slots of finished machines that stored (or are new) ----
+        // ---- write back the slots of finished machines ----
         if (MODE != 0) {
             const uint32_t cnt = r.n < P ? r.n : P;
-            uint64_t fm = __ballot(finish && (wrote || fresh));
+            // a machine that ran a step (or is new) may have stored: its slot goes back
+            uint64_t fm = __ballot(finish && (done > 0 || fresh));
             while (fm) {
                 // kWriteGroup machines: their LDS rows are read before any is stored
                 uint32_t C[kWriteGroup], D[kWriteGroup];
@@ -885,12 +881,13 @@ static hipError_t launch_k3_p(bool pow2, dim3 grid, dim3 block, size_t shmem, hi
 }
 
 // the tape is staged in LDS when every memory fits its slot and every tape
-// is at most kTapeLdsMax words; the region is at least one 16-byte group
+// is at most kTapeLdsMax words; the region holds l + 1 words (the step loop
+// reads word u0 <= l unconditionally), rounded up to 16 bytes
 uint32_t slot_words(uint32_t lds_words, uint32_t max_n, uint32_t max_ell)
 {
     if (lds_words == 0) return 0;
     const bool tl = max_n <= lds_words && max_ell <= kTapeLdsMax;
-    return lds_words + 4u + (tl ? ((max_ell < 1u ? 1u : max_ell) + 3u) & ~3u : 0u);
+    return lds_words + 4u + (tl ? (max_ell + 1u + 3u) & ~3u : 0u);
 }
 
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,

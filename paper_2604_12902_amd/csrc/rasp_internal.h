@@ -77,12 +77,16 @@ struct LaunchShape {
 };
 
 // kernel launchers (rasp_kernels.hip)
-hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
-                         const uint32_t *mem_words, uint32_t def_mem,
-                         const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
-                         uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
-                         uint64_t *n_pad, uint32_t *err, uint32_t *max_n, hipStream_t st);
-// (max_n[0] = max n, [1] = some n not a power of two, [2] = max l)
+// Layout of a batch from a device descriptor: n, l, s per machine (b.n,
+// b.ell, b.s), the exclusive offsets b.mem_off (padded n), b.t_off, b.y_off,
+// totals[0..3] = sums of padded n, l, s and n, err |= descriptor error bits,
+// mx[0] = max n, mx[1] != 0 iff some n is not a power of two, mx[2] = max l.
+// sums holds layout_scratch_words(N) words; mx and totals start at zero.
+hipError_t launch_layout(const uint64_t *prog_off, const uint64_t *tape_off, const uint32_t *mem_words,
+                         uint32_t def_mem, const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
+                         uint64_t N, DevBatch b, uint64_t *sums, uint64_t *totals, uint32_t *err, uint32_t *mx,
+                         hipStream_t st);
+uint64_t layout_scratch_words(uint64_t N);
 hipError_t launch_scan_u64(const uint64_t *in, uint64_t *out_excl, uint64_t N,
                            uint64_t *block_sums, uint64_t *total, hipStream_t st);
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out_excl, uint64_t N,

@@ -1017,88 +1017,7 @@ hipError_t launch_steps_sum(DevBatch b, unsigned long long *out, hipStream_t st)
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// descriptor checks and shapes
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_shapes(const uint64_t *__restrict__ prog_off,
-                                                const uint64_t *__restrict__ tape_off,
-                                                const uint32_t *__restrict__ mem_words, uint32_t def_mem,
-                                                const uint32_t *__restrict__ tape_cap,
-                                                const uint32_t *__restrict__ out_cap, uint32_t def_out,
-                                                uint64_t N, uint32_t *__restrict__ n_out,
-                                                uint32_t *__restrict__ ell_out, uint32_t *__restrict__ s_out,
-                                                uint64_t *__restrict__ n_pad, uint32_t *__restrict__ err,
-                                                uint32_t *__restrict__ max_n)
-{
-    const uint64_t v0 = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const bool in = v0 < N;
-    const uint64_t v = in ? v0 : N - 1;                    // out-of-range lanes repeat the last machine
-    uint32_t e = 0;
-    const uint64_t p0 = prog_off[v], p1 = prog_off[v + 1];
-    const uint64_t t0 = tape_off[v], t1 = tape_off[v + 1];
-    if (p1 < p0 || t1 < t0) e |= kErrOffsets;
-    const uint64_t plen = p1 >= p0 ? p1 - p0 : 0;
-    const uint64_t tlen = t1 >= t0 ? t1 - t0 : 0;
-    const uint32_t n = mem_words ? mem_words[v] : def_mem;
-    const uint64_t ell = tape_cap ? static_cast<uint64_t>(tape_cap[v]) : tlen;
-    const uint32_t s = out_cap ? out_cap[v] : def_out;
-    if (n == 0 || n > kMaxMemWords) e |= kErrMemSize;
-    if (plen > n) e |= kErrProgTooLong;
-    if (tlen > ell || ell > 0x7fffffffull) e |= kErrTapeTooLong;
-    if (s > 0x7fffffffu) e |= kErrMemSize;
-    if (in) {
-        n_out[v] = n;
-        ell_out[v] = static_cast<uint32_t>(ell);
-        s_out[v] = s;
-        n_pad[v] = (static_cast<uint64_t>(n) + 3ull) & ~3ull;
-    }
-    if (e) atomicOr(err, e);
-    (void)max_n;
-}
-
-// maximum memory size and "some size is not a power of two": a fixed grid
-// of 256 blocks, grid-stride, one atomic per block; out[0] = max, out[1] != 0
-// iff some n is not a power of two
-__global__ __launch_bounds__(256) void k_max_u32(const uint32_t *__restrict__ in, uint64_t N,
-                                                 uint32_t *__restrict__ out)
-{
-    __shared__ uint32_t wmax[256 / kWave], wor[256 / kWave];
-    uint32_t mx = 0, np2 = 0;
-    for (uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; v < N;
-         v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        const uint32_t n = in[v];
-        mx = max(mx, n);
-        np2 |= (n & (n - 1u)) ? 1u : 0u;
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), off)));
-        np2 |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(np2), off));
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) { wmax[threadIdx.x / kWave] = mx; wor[threadIdx.x / kWave] = np2; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < static_cast<int>(blockDim.x / kWave); ++w) { mx = max(mx, wmax[w]); np2 |= wor[w]; }
-        atomicMax(out, mx);
-        if (np2) atomicOr(out + 1, 1u);
-    }
-}
-
-hipError_t launch_shapes(const uint64_t *prog_off, const uint64_t *tape_off,
-                         const uint32_t *mem_words, uint32_t def_mem,
-                         const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
-                         uint64_t N, uint32_t *n, uint32_t *ell, uint32_t *s,
-                         uint64_t *n_pad, uint32_t *err, uint32_t *max_n, hipStream_t st)
-{
-    k_shapes<<<static_cast<unsigned>((N + 255) / 256), 256, 0, st>>>(
-        prog_off, tape_off, mem_words, def_mem, tape_cap, out_cap, def_out, N, n, ell, s, n_pad, err, max_n);
-    hipError_t e = hipGetLastError();
-    if (e) return e;
-    k_max_u32<<<256, 256, 0, st>>>(n, N, max_n);
-    k_max_u32<<<256, 256, 0, st>>>(ell, N, max_n + 2);          // max l at max_n[2]
-    return hipGetLastError();
-}
-
+// checks of a loaded state: u0 <= l, y0 <= s, and i, a w-bit words
 __global__ __launch_bounds__(256) void k_check_state(DevBatch b, uint32_t *err)
 {
     const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1265,6 +1184,141 @@ hipError_t launch_scan_u32(const uint32_t *in, uint64_t *out, uint64_t N, uint64
                            uint64_t *total, hipStream_t st)
 {
     return scan_impl<uint32_t>(in, out, N, sums, total, st);
+}
+
+// ---------------------------------------------------------------------------
+// Batch layout from a device descriptor in three launches: per tile of
+// kScanTile machines the shapes, checks, column sums (padded n, l, s, n) and
+// maxima; one block scanning the four columns of tile sums; per tile the
+// exclusive offsets of the padded memory, tape and output slices.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kScanBlock) void k_layout_tiles(
+    const uint64_t *__restrict__ prog_off, const uint64_t *__restrict__ tape_off,
+    const uint32_t *__restrict__ mem_words, uint32_t def_mem, const uint32_t *__restrict__ tape_cap,
+    const uint32_t *__restrict__ out_cap, uint32_t def_out, uint64_t N, uint32_t *__restrict__ n_out,
+    uint32_t *__restrict__ ell_out, uint32_t *__restrict__ s_out, uint64_t *__restrict__ sums, uint64_t nb,
+    uint32_t *__restrict__ err, uint32_t *__restrict__ mx)
+{
+    __shared__ uint64_t part[4][kScanBlock / kWave];
+    __shared__ uint32_t pmax[3][kScanBlock / kWave];
+    const uint64_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint64_t x[4] = {0, 0, 0, 0};
+    uint32_t e = 0, maxn = 0, np2 = 0, maxl = 0;
+    for (int it = 0; it < kScanItems; ++it) {
+        const uint64_t v = base + it;
+        if (v >= N) break;
+        const uint64_t p0 = prog_off[v], p1 = prog_off[v + 1];
+        const uint64_t t0 = tape_off[v], t1 = tape_off[v + 1];
+        if (p1 < p0 || t1 < t0) e |= kErrOffsets;
+        const uint64_t plen = p1 >= p0 ? p1 - p0 : 0;
+        const uint64_t tlen = t1 >= t0 ? t1 - t0 : 0;
+        const uint32_t n = mem_words ? mem_words[v] : def_mem;
+        const uint64_t ell = tape_cap ? static_cast<uint64_t>(tape_cap[v]) : tlen;
+        const uint32_t s = out_cap ? out_cap[v] : def_out;
+        if (n == 0 || n > kMaxMemWords) e |= kErrMemSize;
+        if (plen > n) e |= kErrProgTooLong;
+        if (tlen > ell || ell > 0x7fffffffull) e |= kErrTapeTooLong;
+        if (s > 0x7fffffffu) e |= kErrMemSize;
+        n_out[v] = n;
+        ell_out[v] = static_cast<uint32_t>(ell);
+        s_out[v] = s;
+        x[0] += (static_cast<uint64_t>(n) + 3ull) & ~3ull;
+        x[1] += ell;
+        x[2] += s;
+        x[3] += n;
+        maxn = max(maxn, n);
+        np2 |= (n & (n - 1u)) ? 1u : 0u;
+        maxl = max(maxl, static_cast<uint32_t>(ell < 0xffffffffull ? ell : 0xffffffffull));
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        for (int c = 0; c < 4; ++c) x[c] += __shfl_xor(x[c], off);
+        maxn = max(maxn, static_cast<uint32_t>(__shfl_xor(static_cast<int>(maxn), off)));
+        maxl = max(maxl, static_cast<uint32_t>(__shfl_xor(static_cast<int>(maxl), off)));
+        np2 |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(np2), off));
+        e |= static_cast<uint32_t>(__shfl_xor(static_cast<int>(e), off));
+    }
+    const uint32_t w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        for (int c = 0; c < 4; ++c) part[c][w] = x[c];
+        pmax[0][w] = maxn; pmax[1][w] = np2 | (e << 1); pmax[2][w] = maxl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint64_t t = 0;
+        for (int k = 0; k < kScanBlock / kWave; ++k) t += part[threadIdx.x][k];
+        sums[threadIdx.x * nb + blockIdx.x] = t;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t m0 = 0, f = 0, m2 = 0;
+        for (int k = 0; k < kScanBlock / kWave; ++k) { m0 = max(m0, pmax[0][k]); f |= pmax[1][k]; m2 = max(m2, pmax[2][k]); }
+        atomicMax(mx, m0);
+        if (f & 1u) atomicOr(mx + 1, 1u);
+        atomicMax(mx + 2, m2);
+        if (f >> 1) atomicOr(err, f >> 1);
+    }
+}
+
+// exclusive scan of the four columns of tile sums (in place); totals out
+__global__ __launch_bounds__(kScanBlock) void k_layout_sums(uint64_t *sums, uint64_t nb, uint64_t *totals)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    for (int c = 0; c < 4; ++c) {
+        uint64_t *col = sums + c * nb;
+        uint64_t carry = 0;
+        for (uint64_t b0 = 0; b0 < nb; b0 += kScanBlock) {
+            const uint64_t idx = b0 + threadIdx.x;
+            const uint64_t x = idx < nb ? col[idx] : 0;
+            uint64_t total;
+            const uint64_t ex = block_exclusive<uint64_t>(x, tmp, total);
+            if (idx < nb) col[idx] = carry + ex;
+            carry += total;
+        }
+        if (threadIdx.x == 0) totals[c] = carry;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_layout_apply(
+    const uint32_t *__restrict__ n, const uint32_t *__restrict__ ell, const uint32_t *__restrict__ s,
+    uint64_t N, const uint64_t *__restrict__ sums, uint64_t nb, uint64_t *__restrict__ mem_off,
+    uint64_t *__restrict__ t_off, uint64_t *__restrict__ y_off)
+{
+    __shared__ uint64_t tmp[kScanBlock / kWave];
+    const uint64_t base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint64_t vn[kScanItems], vl[kScanItems], vs[kScanItems];
+    uint64_t xn = 0, xl = 0, xs = 0;
+    for (int it = 0; it < kScanItems; ++it) {
+        const bool in = base + it < N;
+        vn[it] = in ? (static_cast<uint64_t>(n[base + it]) + 3ull) & ~3ull : 0;
+        vl[it] = in ? ell[base + it] : 0;
+        vs[it] = in ? s[base + it] : 0;
+        xn += vn[it]; xl += vl[it]; xs += vs[it];
+    }
+    uint64_t total;
+    uint64_t rn = sums[blockIdx.x] + block_exclusive<uint64_t>(xn, tmp, total);
+    uint64_t rl = sums[nb + blockIdx.x] + block_exclusive<uint64_t>(xl, tmp, total);
+    uint64_t rs = sums[2 * nb + blockIdx.x] + block_exclusive<uint64_t>(xs, tmp, total);
+    for (int it = 0; it < kScanItems; ++it) {
+        if (base + it < N) { mem_off[base + it] = rn; t_off[base + it] = rl; y_off[base + it] = rs; }
+        rn += vn[it]; rl += vl[it]; rs += vs[it];
+    }
+}
+
+uint64_t layout_scratch_words(uint64_t N) { return 4 * ((N + kScanTile - 1) / kScanTile) + 4; }
+
+hipError_t launch_layout(const uint64_t *prog_off, const uint64_t *tape_off, const uint32_t *mem_words,
+                         uint32_t def_mem, const uint32_t *tape_cap, const uint32_t *out_cap, uint32_t def_out,
+                         uint64_t N, DevBatch b, uint64_t *sums, uint64_t *totals, uint32_t *err, uint32_t *mx,
+                         hipStream_t st)
+{
+    const uint64_t nb = (N + kScanTile - 1) / kScanTile;
+    k_layout_tiles<<<static_cast<unsigned>(nb), kScanBlock, 0, st>>>(prog_off, tape_off, mem_words, def_mem,
+                                                                     tape_cap, out_cap, def_out, N, b.n, b.ell,
+                                                                     b.s, sums, nb, err, mx);
+    k_layout_sums<<<1, kScanBlock, 0, st>>>(sums, nb, totals);
+    k_layout_apply<<<static_cast<unsigned>(nb), kScanBlock, 0, st>>>(b.n, b.ell, b.s, N, sums, nb, b.mem_off,
+                                                                     b.t_off, b.y_off);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -473,22 +473,15 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
         arena_free(c, &staging);
     } else {
         // device descriptor: checks, shapes and offsets computed on the device
-        const uint64_t nsc = scan_scratch_words(N);
-        const uint64_t tb = align_up(8 * N, kAlign) + 3 * align_up(8 * nsc, kAlign) + kAlign;
+        const uint64_t tb = align_up(8 * layout_scratch_words(N), kAlign) + kAlign;
         if (!arena_alloc(c, tb, &staging)) { fail(c, RASP_E_NOMEM, "arena cannot hold load scratch"); return bail(RASP_E_NOMEM); }
         char *sp = at<char>(c, staging);
-        uint64_t *n_pad = reinterpret_cast<uint64_t *>(sp);
-        uint64_t *sums = reinterpret_cast<uint64_t *>(sp + align_up(8 * N, kAlign));
-        uint64_t *tots = reinterpret_cast<uint64_t *>(sp + align_up(8 * N, kAlign) + 3 * align_up(8 * nsc, kAlign));
+        uint64_t *sums = reinterpret_cast<uint64_t *>(sp);
+        uint64_t *tots = reinterpret_cast<uint64_t *>(sp + align_up(8 * layout_scratch_words(N), kAlign));
         uint32_t *errw = reinterpret_cast<uint32_t *>(tots + 4);
         hipError_t e = hipMemsetAsync(tots, 0, kAlign, st);
-        if (!e) e = launch_shapes(d->prog_off, d->tape_off, d->mem_words, d->default_mem_words, d->tape_cap,
-                                  d->out_cap, d->default_out_cap, N, B->dev.n, B->dev.ell, B->dev.s, n_pad, errw,
-                                  errw + 1, st);
-        if (!e) e = launch_scan_u64(n_pad, B->dev.mem_off, N, sums, &tots[0], st);
-        if (!e) e = launch_scan_u32(B->dev.ell, B->dev.t_off, N, sums + align_up(8 * nsc, kAlign) / 8, &tots[1], st);
-        if (!e) e = launch_scan_u32(B->dev.s, B->dev.y_off, N, sums + 2 * align_up(8 * nsc, kAlign) / 8, &tots[2], st);
-        if (!e) e = launch_scan_u32(B->dev.n, n_pad, N, sums, &tots[3], st);   // dense total into tots[3]
+        if (!e) e = launch_layout(d->prog_off, d->tape_off, d->mem_words, d->default_mem_words, d->tape_cap,
+                                  d->out_cap, d->default_out_cap, N, B->dev, sums, tots, errw, errw + 1, st);
         if (!e) e = launch_check_words_off(d->prog, d->prog_off, N, B->dev.wshift, errw, st);
         if (!e) e = launch_check_words_off(d->tape, d->tape_off, N, B->dev.wshift, errw, st);
         if (!e) e = hipMemcpyAsync(c->tot_host, tots, 4 * sizeof(uint64_t) + 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);

@@ -124,6 +124,9 @@ void init_kernel_attributes();
 hipError_t launch_running(const BatchTable *tab, uint64_t total, unsigned long long *counts,
                           hipStream_t st);
 hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st);
+// per-machine scalars into device buffers (null pointers skipped)
+hipError_t launch_fetch_scalars(DevBatch b, uint8_t *status, uint64_t *steps, int32_t *i, int32_t *a,
+                                uint32_t *u0, uint32_t *y0, hipStream_t st);
 hipError_t launch_steps_sum(DevBatch b, unsigned long long *out, hipStream_t st);
 hipError_t launch_gather_words(const int32_t *src, const uint64_t *off, const uint32_t *len,
                                uint64_t N, int32_t *dst, const uint64_t *dst_off,

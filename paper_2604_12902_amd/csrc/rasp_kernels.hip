@@ -1017,6 +1017,28 @@ hipError_t launch_steps_sum(DevBatch b, unsigned long long *out, hipStream_t st)
     return hipGetLastError();
 }
 
+// per-machine scalars into caller device buffers (any pointer may be null):
+// one launch instead of one copy per field
+__global__ __launch_bounds__(256) void k_fetch_scalars(DevBatch b, uint8_t *status, uint64_t *steps, int32_t *i,
+                                                       int32_t *a, uint32_t *u0, uint32_t *y0)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= b.N) return;
+    if (status) status[v] = b.status[v];
+    if (steps) steps[v] = b.steps[v];
+    if (i) i[v] = b.i[v];
+    if (a) a[v] = b.a[v];
+    if (u0) u0[v] = b.u0[v];
+    if (y0) y0[v] = b.y0[v];
+}
+
+hipError_t launch_fetch_scalars(DevBatch b, uint8_t *status, uint64_t *steps, int32_t *i, int32_t *a,
+                                uint32_t *u0, uint32_t *y0, hipStream_t st)
+{
+    k_fetch_scalars<<<static_cast<unsigned>((b.N + 255) / 256), 256, 0, st>>>(b, status, steps, i, a, u0, y0);
+    return hipGetLastError();
+}
+
 // checks of a loaded state: u0 <= l, y0 <= s, and i, a w-bit words
 __global__ __launch_bounds__(256) void k_check_state(DevBatch b, uint32_t *err)
 {

@@ -1037,12 +1037,18 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
         HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_probe(b->dev, st); }));
         b->status_stale = false;
     }
-    if (o->status) HIPCHK(c, hipMemcpyAsync(o->status, b->dev.status, N, kind, st));
-    if (o->steps) HIPCHK(c, hipMemcpyAsync(o->steps, b->dev.steps, 8 * N, kind, st));
-    if (o->i) HIPCHK(c, hipMemcpyAsync(o->i, b->dev.i, 4 * N, kind, st));
-    if (o->a) HIPCHK(c, hipMemcpyAsync(o->a, b->dev.a, 4 * N, kind, st));
-    if (o->u0) HIPCHK(c, hipMemcpyAsync(o->u0, b->dev.u0, 4 * N, kind, st));
-    if (o->y0) HIPCHK(c, hipMemcpyAsync(o->y0, b->dev.y0, 4 * N, kind, st));
+    if (kind == hipMemcpyDeviceToDevice) {
+        if (o->status || o->steps || o->i || o->a || o->u0 || o->y0)
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] {
+                return launch_fetch_scalars(b->dev, o->status, o->steps, o->i, o->a, o->u0, o->y0, st); }));
+    } else {
+        if (o->status) HIPCHK(c, hipMemcpyAsync(o->status, b->dev.status, N, kind, st));
+        if (o->steps) HIPCHK(c, hipMemcpyAsync(o->steps, b->dev.steps, 8 * N, kind, st));
+        if (o->i) HIPCHK(c, hipMemcpyAsync(o->i, b->dev.i, 4 * N, kind, st));
+        if (o->a) HIPCHK(c, hipMemcpyAsync(o->a, b->dev.a, 4 * N, kind, st));
+        if (o->u0) HIPCHK(c, hipMemcpyAsync(o->u0, b->dev.u0, 4 * N, kind, st));
+        if (o->y0) HIPCHK(c, hipMemcpyAsync(o->y0, b->dev.y0, 4 * N, kind, st));
+    }
     if (o->y && b->sum_s) HIPCHK(c, hipMemcpyAsync(o->y, b->dev.Y, 4 * b->sum_s, kind, st));
     Alloc tmp;
     if (o->mem_digest) {

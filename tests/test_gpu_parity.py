@@ -506,3 +506,41 @@ def test_narrow_words_reject_wide_values(ctx, rasp):
         ctx.load(bad_w)
     assert e.value.code == R.RASP_E_INVAL
     compare(run_gpu(ctx, ok, 256), oracle.run(ok, 256, w=8))
+
+
+def test_fetch_into_device_buffers(ctx, rasp):
+    """rasp_fetch_outputs with RASP_OUT_DEVICE_PTRS (what the benchmark times)
+    gives the same scalars, outputs and memory as the host fetch, field by
+    field and with some fields left out."""
+    import torch
+    R = rasp
+    configure(ctx, rasp, "firstpass-lds64")
+    b = W.config3(num_vms=3000, seed=91, budget=800)
+    h = ctx.load(b)
+    ctx.run(h, 800)
+    host = ctx.fetch(h, mem=True)
+    dev = ctx.device
+    N = b.N
+    sum_n = int(b.mem_words.astype(np.int64).sum())
+    bufs = dict(status=torch.empty(N, dtype=torch.uint8, device=dev),
+                steps=torch.empty(N, dtype=torch.int64, device=dev),
+                i=torch.empty(N, dtype=torch.int32, device=dev),
+                a=torch.empty(N, dtype=torch.int32, device=dev),
+                u0=torch.empty(N, dtype=torch.int32, device=dev),
+                y0=torch.empty(N, dtype=torch.int32, device=dev),
+                y=torch.empty(int(b.out_cap.astype(np.int64).sum()), dtype=torch.int32, device=dev),
+                mem=torch.empty(sum_n, dtype=torch.int32, device=dev))
+    R.rasp_fetch_outputs_into(ctx.handle, h, bufs, device=True)
+    torch.cuda.synchronize()
+    for k in ("status", "steps", "i", "a", "u0", "y0", "y", "mem"):
+        got = bufs[k].cpu().numpy()
+        want = np.asarray(host[k])
+        assert np.array_equal(got.view(want.dtype) if got.dtype != want.dtype else got, want), k
+    # a subset of fields: the others stay untouched
+    part = dict(steps=torch.full((N,), -7, dtype=torch.int64, device=dev),
+                a=torch.full((N,), -7, dtype=torch.int32, device=dev))
+    R.rasp_fetch_outputs_into(ctx.handle, h, part, device=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(part["steps"].cpu().numpy().view(np.uint64), np.asarray(host["steps"]))
+    assert np.array_equal(part["a"].cpu().numpy(), np.asarray(host["a"]))
+    ctx.free(h)

@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--lds-words", type=int, default=None)
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
+    ap.add_argument("--first-pass-kind", type=int, default=None, choices=[0, 1])
     ap.add_argument("--lazy", action="store_true",
                     help="build c0 inside the run (RASP_DESC_LAZY) instead of in rasp_load_batch")
     ap.add_argument("--no-autotune", action="store_true",
@@ -267,6 +268,8 @@ def main():
             ctx.set(R.RASP_OPT_EPOCH, args.epoch)
         if args.waves_per_cu is not None:
             ctx.set(R.RASP_OPT_WAVES_PER_CU, args.waves_per_cu)
+        if args.first_pass_kind is not None:
+            ctx.set(R.RASP_OPT_FIRST_PASS_KIND, args.first_pass_kind)
 
     def one_step(keep=False):
         h = R.rasp_load_batch(ctx.handle, desc)

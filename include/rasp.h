@@ -262,7 +262,9 @@ int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
  *                          RASP_SCHED_AUTO (default): the autotuned choice.
  *   RASP_OPT_EPOCH         steps a lane runs between refill checks (q), >= 1
  *   RASP_OPT_LDS_WORDS     memory words per machine staged in LDS by the
- *                          persistent kernel (0 = none), power of two <= 1024
+ *                          persistent kernel (0 = none), a multiple of 4 in
+ *                          [4, 1024]; -1 (default): n rounded up to 4 when
+ *                          two waves of such slots fit in LDS, else 0
  *   RASP_OPT_WAVES_PER_CU  resident waves per compute unit for the persistent
  *                          kernel
  *   RASP_OPT_GRAPH         1: capture the launch sequence of a run (queue reset,

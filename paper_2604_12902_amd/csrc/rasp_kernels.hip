@@ -91,6 +91,16 @@ struct GlobalMem {                       // every word in HBM
         return v;
     }
     __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const { if (en) M[k] = v; }
+    // one transition's memory traffic in program order: the current
+    // instruction's store, its data word, then the next instruction's words
+    __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
+                                         uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        st(jj, w, st_en);
+        d = ld_data(jj, need);
+        o = ld(np);
+        j = ld(nq);
+    }
 };
 
 struct LdsMem {                          // whole memory in the lane's LDS slot (n <= P)
@@ -102,6 +112,14 @@ struct LdsMem {                          // whole memory in the lane's LDS slot 
     __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
     {
         rasp_lds[en ? base + k : spare] = v;
+    }
+    __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
+                                         uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        st(jj, w, st_en);
+        d = ld_data(jj, need);
+        o = ld(np);
+        j = ld(nq);
     }
 };
 
@@ -124,6 +142,27 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
     {
         if (en) { if (k < P) rasp_lds[base + k] = v; else M[k] = v; }
+    }
+    // When no active lane touches a word at or above P in this transition
+    // (the common case once a program and its data sit below P), one
+    // wave-uniform branch selects straight LDS accesses; otherwise each
+    // access picks LDS or HBM per lane.  The spare word after the P memory
+    // words takes the stores of lanes that do not store.
+    __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
+                                         uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        const bool far = ((st_en | need) & (jj >= P)) | (np >= P) | (nq >= P);
+        if (__builtin_expect(__ballot(far) != 0, 0)) {
+            st(jj, w, st_en);
+            d = ld_data(jj, need);
+            o = ld(np);
+            j = ld(nq);
+        } else {
+            rasp_lds[st_en ? base + jj : base + P] = w;
+            d = rasp_lds[base + (jj < P ? jj : 0u)];
+            o = rasp_lds[base + np];
+            j = rasp_lds[base + nq];
+        }
     }
 };
 
@@ -230,18 +269,24 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             jj = static_cast<uint32_t>(j);
             seq = p + 2u;
             seq = seq >= n ? seq - n : seq;
+            np = taken ? jj : seq;
+            nq = np + 1u;
+            nq = nq == n ? 0u : nq;
             // with w < 32 a jump target j < n can also be the largest word,
             // whose operand position i + 1 wraps
             bool rare = (static_cast<uint32_t>(j) >= n) | (i >= imax - 3) | (n < 2u);
             if (WM) rare |= j >= imax - 3;
-            if (rare) {
-                jj = cmod(j, n);
-                seq = advance_pos(i, p, n, imax, WM ? ws : 0u);
+            // wave-uniform and out of line: when some lane needs the general
+            // positions every lane computes them and the rare lanes take them
+            if (__builtin_expect(__ballot(rare) != 0, 0)) {
+                const uint32_t jj2 = cmod(j, n);
+                const uint32_t seq2 = advance_pos(i, p, n, imax, WM ? ws : 0u);
+                const uint32_t np2 = taken ? jj2 : seq2;
+                const uint32_t nq2 = operand_pos(ni, np2, n, imax);
+                jj = rare ? jj2 : jj;
+                np = rare ? np2 : np;
+                nq = rare ? nq2 : nq;
             }
-            np = taken ? jj : seq;
-            nq = np + 1u;
-            nq = nq == n ? 0u : nq;
-            if (rare) nq = operand_pos(ni, np, n, imax);
         }
 
         const bool st_en = (op == 4u) | rd_ok;
@@ -251,13 +296,11 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         } else if (rd_ok) {
             w = tape.ld(u0);
         }
-        mem.st(jj, w, st_en);
         u0 += rd_ok ? 1u : 0u;
         const bool need = (op == 2u) | (op == 3u) | (op == 7u);
-        const int32_t d = mem.ld_data(jj, need);
         const int32_t jcur = j;
-        o = mem.ld(np);
-        j = mem.ld(nq);
+        int32_t d;
+        mem.step(jj, w, st_en, need, np, nq, d, o, j);
         if (Tape::kLds) tv = tape.ld(u0);
 
         const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);

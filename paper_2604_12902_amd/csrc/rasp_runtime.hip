@@ -522,8 +522,8 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
 }
 
 // LDS words per machine slot for a launch whose largest memory is max_n:
-// the option, or (option -1) the smallest power of two holding the whole
-// memory if two waves of such slots fit a compute unit, else none
+// the option, or (option -1) the whole memory rounded up to 4 words if two
+// waves of such slots fit a compute unit, else none
 uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n, uint32_t max_ell = 0)
 {
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
@@ -531,12 +531,27 @@ uint32_t lds_words_for(rasp_ctx *c, uint32_t max_n, uint32_t max_ell = 0)
     if (c->lds_words >= 0) {
         P = static_cast<uint32_t>(c->lds_words);
     } else {
-        P = 4;
-        while (P < max_n && P < 1024) P <<= 1;
-        if (P < max_n || 2ull * kWave * slot_words(P, max_n, max_ell) * 4 > lds) P = 0;
+        P = max_n <= 1024 ? std::max<uint32_t>(4, (max_n + 3u) & ~3u) : 0u;
+        if (P && 2ull * kWave * slot_words(P, max_n, max_ell) * 4 > lds) P = 0;
     }
-    while (P && static_cast<uint64_t>(kWave) * slot_words(P, max_n, max_ell) * 4 > lds) P >>= 1;
+    while (P && static_cast<uint64_t>(kWave) * slot_words(P, max_n, max_ell) * 4 > lds) P = (P >> 1) & ~3u;
     return P;
+}
+
+// waves per block (1..4) of a persistent launch whose lanes hold slots of SPw
+// LDS words: the one that keeps the most waves of a compute unit resident
+// (ties to the larger block).  With 208-word slots, for instance, three
+// one-wave blocks fit where one two-wave block does.
+uint32_t waves_per_block_for(uint32_t SPw, uint64_t lds)
+{
+    if (SPw == 0) return 4;
+    uint32_t wpb = 1;
+    uint64_t best = 0;
+    for (uint32_t w = 4; w >= 1; --w) {
+        const uint64_t resident = lds / (static_cast<uint64_t>(w) * kWave * SPw * 4) * w;
+        if (resident > best) { best = resident; wpb = w; }
+    }
+    return wpb;
 }
 
 // drop captured graphs (all of them, or those that use batch h)
@@ -672,8 +687,7 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     const uint32_t P = lds_words_for(c, max_n, max_ell);
     const uint64_t lds = static_cast<uint64_t>(c->lds_bytes);
     const uint32_t SPw = slot_words(P, max_n, max_ell);
-    uint32_t wpb = 4;
-    while (P && wpb > 1 && static_cast<uint64_t>(wpb) * kWave * SPw * 4 > lds) wpb >>= 1;
+    const uint32_t wpb = waves_per_block_for(SPw, lds);
     const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
     const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
     const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
@@ -1174,8 +1188,8 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
         if (value < 1 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "epoch must be >= 1");
         c->epoch = value; return RASP_OK;
     case RASP_OPT_LDS_WORDS:
-        if (value < -1 || value > 1024 || (value > 0 && ((value & (value - 1)) || value < 4)))
-            return fail(c, RASP_E_INVAL, "lds words must be -1 (auto), 0 or a power of two in [4, 1024]");
+        if (value < -1 || value > 1024 || (value > 0 && (value & 3)))
+            return fail(c, RASP_E_INVAL, "lds words must be -1 (auto), 0 or a multiple of 4 in [4, 1024]");
         c->lds_words = value; return RASP_OK;
     case RASP_OPT_WAVES_PER_CU:
         if (value < 1 || value > 32) return fail(c, RASP_E_INVAL, "waves per CU must be in [1, 32]");
@@ -1343,9 +1357,19 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         return RASP_OK;
     };
     // candidate values; one knob at a time from the current setting
-    const int64_t full = [&]() { int64_t P = 4; while (P < b->max_n && P < 1024) P <<= 1; return P; }();
+    const int64_t full = std::max<int64_t>(4, (static_cast<int64_t>(b->max_n) + 3) & ~int64_t(3));
     std::vector<int64_t> lds_c = {0, 32, 64, 128, 256};
     if (full <= 1024 && std::find(lds_c.begin(), lds_c.end(), full) == lds_c.end()) lds_c.push_back(full);
+    // and the largest split (low words in LDS, the rest in HBM) that keeps
+    // 3, 4, 6 or 8 waves of a compute unit resident: programs that touch only
+    // their low cells then run from LDS at a higher occupancy.  A slot of a
+    // multiple of 32 words would put the same word of every lane's slot in
+    // one LDS bank, so such a slot gives up 4 words.
+    for (int64_t k : {3, 4, 6, 8}) {
+        int64_t Pk = (static_cast<int64_t>(c->lds_bytes) / (k * kWave * 4) - 4) & ~int64_t(3);
+        if ((Pk + 4) % 32 == 0) Pk -= 4;
+        if (Pk > 0 && Pk < b->max_n && std::find(lds_c.begin(), lds_c.end(), Pk) == lds_c.end()) lds_c.push_back(Pk);
+    }
     const std::vector<int64_t> fp_c = {0, 16, 64, 256}, ep_c = {16, 64, 256, 1024}, wv_c = {8, 16, 32},
                                fk_c = {0, 1};
     int64_t cur[6] = {RASP_SCHED_PERSISTENT, c->lds_words < 0 ? static_cast<int64_t>(lds_words_for(c, b->max_n, b->max_ell)) : c->lds_words,

@@ -25,6 +25,10 @@ SCHEDULES = {
     "firstpass-lds16-tiny-epoch": dict(schedule=2, first_pass=1, lds_words=16, epoch=1, kind=0),
     "ldsfirst-lds64": dict(schedule=2, first_pass=5, lds_words=64, epoch=32, kind=1),
     "ldsfirst-lds1024-epoch3": dict(schedule=2, first_pass=7, lds_words=1024, epoch=3, kind=1),
+    # slots of 208 and 160 words: three one-wave blocks, one four-wave block
+    # per compute unit; memories above 208 / 156 words are split
+    "persistent-lds208-split": dict(schedule=2, first_pass=64, lds_words=208, epoch=64, kind=0),
+    "persistent-lds156-split": dict(schedule=2, first_pass=0, lds_words=156, epoch=16, kind=0),
 }
 
 
@@ -293,6 +297,13 @@ def test_error_paths(ctx, rasp):
         small.load(W.config2(num_vms=20000))
     assert e.value.code == R.RASP_E_NOMEM
     small.close()
+    # LDS words per slot: -1, 0 or a multiple of 4 up to 1024
+    before = ctx.get(R.RASP_OPT_LDS_WORDS)
+    for bad_p in (6, 1028, -2):
+        with pytest.raises(R.RaspError) as e:
+            ctx.set(R.RASP_OPT_LDS_WORDS, bad_p)
+        assert e.value.code == R.RASP_E_INVAL
+    assert ctx.get(R.RASP_OPT_LDS_WORDS) == before
     # the context still works after all of the above
     compare(run_gpu(ctx, b, 256), oracle.run(b, 256))
 
@@ -422,7 +433,8 @@ def test_autotune_on_a_lazy_batch(ctx, rasp):
         ctx.set(R.RASP_OPT_FIRST_PASS_KIND, 0)
 
 
-@pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "firstpass-lds64", "ldsfirst-lds64"])
+@pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "firstpass-lds64", "ldsfirst-lds64",
+                                   "persistent-lds208-split", "persistent-lds156-split"])
 def test_fig1_programs_bit_exact(ctx, rasp, sched):
     """Word RASP, n = 250 (the general-n path), uniform Sec. 2.2 programs with
     the input-reading prologue, budget 10^6: every machine."""

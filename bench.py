@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
     ap.add_argument("--first-pass-kind", type=int, default=None, choices=[0, 1])
+    ap.add_argument("--inflight", type=int, default=1,
+                    help="also time the persistent schedule with this many batches in flight "
+                         "(one context and stream each); 1: skip")
     ap.add_argument("--lazy", action="store_true",
                     help="build c0 inside the run (RASP_DESC_LAZY) instead of in rasp_load_batch")
     ap.add_argument("--no-autotune", action="store_true",
@@ -179,6 +182,83 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
     changed since."""
     from paper_2604_12902_amd import counters
     return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs)
+
+
+def arena_inflight(fp):
+    """Arena of a context that only loads, runs and fetches (no autotune snapshot)."""
+    return int(fp * 1.25) + (256 << 20)
+
+
+def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_steps):
+    """The persistent schedule with `args.inflight` batches in flight, one per
+    context (each context has its own stream): batch k is loaded and launched
+    before batch k-1 is fetched, so the load and first pass of one batch run
+    beside the long tail of the one before.  Every batch does the whole work
+    (load, run, fetch); the outputs of the last batch of each context are
+    checked against the oracle.  Returns throughput and per-batch latency
+    (load issued to outputs fetched)."""
+    n = args.inflight
+    ctxs = [ctx] + [R.Context(arena) for _ in range(n - 1)]
+    for c in ctxs[1:]:
+        for o in (R.RASP_OPT_SCHEDULE, R.RASP_OPT_LDS_WORDS, R.RASP_OPT_FIRST_PASS, R.RASP_OPT_EPOCH,
+                  R.RASP_OPT_WAVES_PER_CU, R.RASP_OPT_FIRST_PASS_KIND):
+            c.set(o, ctx.get(o))
+    dev = torch.device("cuda", 0)
+    N = batch.N
+    ny = int(batch.out_cap.astype(np.int64).sum())
+
+    def new_outs():
+        return dict(status=torch.empty(N, dtype=torch.uint8, device=dev),
+                    steps=torch.empty(N, dtype=torch.int64, device=dev),
+                    i=torch.empty(N, dtype=torch.int32, device=dev),
+                    a=torch.empty(N, dtype=torch.int32, device=dev),
+                    u0=torch.empty(N, dtype=torch.int32, device=dev),
+                    y0=torch.empty(N, dtype=torch.int32, device=dev),
+                    y=torch.empty(ny, dtype=torch.int32, device=dev))
+    outs = [new_outs() for _ in range(n)]
+
+    def run(steps):
+        pending, lat = [], []
+        for k in range(steps):
+            c = k % n
+            t_issue = time.perf_counter()
+            h = R.rasp_load_batch(ctxs[c].handle, desc)
+            R.rasp_run(ctxs[c].handle, h, budget)
+            pending.append((c, h, t_issue))
+            if len(pending) == n:
+                c0, h0, t0 = pending.pop(0)
+                R.rasp_fetch_outputs_into(ctxs[c0].handle, h0, outs[c0], device=True)
+                R.rasp_free_batch(ctxs[c0].handle, h0)
+                lat.append(time.perf_counter() - t0)
+        for c0, h0, t0 in pending:
+            R.rasp_fetch_outputs_into(ctxs[c0].handle, h0, outs[c0], device=True)
+            R.rasp_free_batch(ctxs[c0].handle, h0)
+            lat.append(time.perf_counter() - t0)
+        return np.array(lat)
+
+    run(max(args.warmup, n))
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    lat = run(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    if args.verify != "none":
+        for c in range(n):
+            for k in ("status", "steps", "i", "a", "u0", "y0"):
+                got = outs[c][k].cpu().numpy()
+                if not np.array_equal(got.astype(getattr(ref, k).dtype), getattr(ref, k)):
+                    raise SystemExit("bench: NOT bit-exact with %d batches in flight: %s" % (n, k))
+            if not np.array_equal(outs[c]["y"].cpu().numpy(), ref.Y):
+                raise SystemExit("bench: NOT bit-exact with %d batches in flight: output words" % n)
+    for c in ctxs[1:]:
+        c.close()
+    res = {"batches_in_flight": n, "value": total_steps / (wall / args.steps),
+           "ms_per_step": 1e3 * wall / args.steps,
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "bit_exact": args.verify != "none"}
+    print("bench: inflight=%d %.3f ms/step  %.3e steps/s  batch latency p50 %.3f p99 %.3f ms" % (
+        n, res["ms_per_step"], res["value"], res["p50_ms"], res["p99_ms"]), flush=True)
+    return res
 
 
 def main():
@@ -334,6 +414,11 @@ def main():
             {k: "%.3f ms x%d" % (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1]}),
             flush=True)
 
+    inflight = None
+    if args.inflight > 1:
+        inflight = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
+                                  total_steps)
+
     head = results["persistent"]
     kt = head["kernels"]
     # dominant kernel of the headline schedule: largest total time
@@ -399,6 +484,7 @@ def main():
         "bit_exact": args.verify,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "inflight": inflight,
     }
     if args.json_extra:
         with open(args.json_extra, "w") as f:

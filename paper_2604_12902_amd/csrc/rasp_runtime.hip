@@ -1337,23 +1337,30 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
+    // one trial: the best of up to three runs from the snapshot while a run
+    // takes under 20 ms (short runs are the noisy ones), else one run
     auto trial_ms = [&](double *ms) -> int {
-        if (lazy) {
-            trial.dev.fresh = 1;
-        } else {
-            hipError_t x = copy_batch(snap.dev, trial.dev);
-            if (x) return fail(c, RASP_E_DEVICE, "autotune restore: %s", hipGetErrorString(x));
-            trial.status_stale = snap.status_stale;
+        double best_run = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (lazy) {
+                trial.dev.fresh = 1;
+            } else {
+                hipError_t x = copy_batch(snap.dev, trial.dev);
+                if (x) return fail(c, RASP_E_DEVICE, "autotune restore: %s", hipGetErrorString(x));
+                trial.status_stale = snap.status_stale;
+            }
+            Batch *tb = &trial;
+            HIPCHK(c, hipEventRecord(e0, st));
+            int r2 = run_batches(c, &tb, &bud, 1);
+            if (r2) return r2;
+            HIPCHK(c, hipEventRecord(e1, st));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float f = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
+            best_run = std::min(best_run, static_cast<double>(f));
+            if (f >= 20.f) break;
         }
-        Batch *tb = &trial;
-        HIPCHK(c, hipEventRecord(e0, st));
-        int r2 = run_batches(c, &tb, &bud, 1);
-        if (r2) return r2;
-        HIPCHK(c, hipEventRecord(e1, st));
-        HIPCHK(c, hipEventSynchronize(e1));
-        float f = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
-        *ms = f;
+        *ms = best_run;
         return RASP_OK;
     };
     // candidate values; one knob at a time from the current setting

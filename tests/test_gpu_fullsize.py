@@ -20,9 +20,11 @@ def R():
     return rasp
 
 
-def _run(R, b, arena_extra=1.2):
+def _run(R, b, arena_extra=1.2, knobs=None):
     d = R.make_desc(b)
     ctx = R.Context(int(R.rasp_batch_footprint(d) * arena_extra) + (64 << 20))
+    for opt, val in (knobs or {}).items():
+        ctx.set(opt, val)
     h = R.rasp_load_batch(ctx.handle, d)
     ctx.run(h, b.budget)
     got = ctx.fetch(h, digest=True)
@@ -56,10 +58,14 @@ def test_plain_scale_every_machine(R):
     assert info["steps_sum"] == int(want.steps.sum())
 
 
-def test_uneven_batch_full_size_sampled(R):
+@pytest.mark.parametrize("slots", ["default", "split32"])
+def test_uneven_batch_full_size_sampled(R, slots):
+    """4,194,304 machines, n 64-1,024: default knobs (memories in HBM), and
+    the 32-word split slots the autotuner picks for this workload."""
     b = W.config3()
-    print("case: uneven N=%d" % b.N, flush=True)
-    got, info = _run(R, b)
+    print("case: uneven N=%d slots=%s" % (b.N, slots), flush=True)
+    knobs = {R.RASP_OPT_LDS_WORDS: 32} if slots == "split32" else None
+    got, info = _run(R, b, knobs=knobs)
     rng = np.random.Generator(np.random.PCG64(7))
     idx = np.sort(rng.choice(b.N, 3000, replace=False))
     # include the slowest machines the GPU reports, to cover the long tail
@@ -81,13 +87,17 @@ def test_rollouts_full_size_sampled(R):
     assert (got["status"] == 1).all()
 
 
-def test_fig1_workload_sampled(R):
+@pytest.mark.parametrize("slots", ["whole", "split152"])
+def test_fig1_workload_sampled(R, slots):
     """The Sec. 3 evaluation's shape: uniform L = 100 programs, word RASP,
     n = 250 (not a power of two), budget 10^6; 65,536 machines, a seeded
-    sample plus the first 2,000 machines."""
+    sample plus the first 2,000 machines.  'whole': default slots (every
+    memory in LDS, 2 waves per CU); 'split152': the slots the autotuner picks
+    for this workload (words 0-151 in LDS, the rest in HBM, 4 waves per CU)."""
     b = W.fig1(num_vms=1 << 16)
-    print("case: fig1 N=%d" % b.N, flush=True)
-    got, info = _run(R, b)
+    print("case: fig1 N=%d slots=%s" % (b.N, slots), flush=True)
+    knobs = {R.RASP_OPT_LDS_WORDS: 152} if slots == "split152" else None
+    got, info = _run(R, b, knobs=knobs)
     rng = np.random.Generator(np.random.PCG64(9))
     idx = np.unique(np.concatenate([np.sort(rng.choice(b.N, 1500, replace=False)),
                                     np.arange(2000)]))

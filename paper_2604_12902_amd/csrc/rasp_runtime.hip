@@ -1368,11 +1368,13 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     std::vector<int64_t> lds_c = {0, 32, 64, 128, 256};
     if (full <= 1024 && std::find(lds_c.begin(), lds_c.end(), full) == lds_c.end()) lds_c.push_back(full);
     // and the largest split (low words in LDS, the rest in HBM) that keeps
-    // 3, 4, 6 or 8 waves of a compute unit resident: programs that touch only
-    // their low cells then run from LDS at a higher occupancy.  A slot of a
-    // multiple of 32 words would put the same word of every lane's slot in
-    // one LDS bank, so such a slot gives up 4 words.
-    for (int64_t k : {3, 4, 6, 8}) {
+    // k waves of a compute unit resident: programs that touch only their low
+    // cells then run from LDS at a higher occupancy, and memories far larger
+    // than any slot keep their hottest low words in LDS at the occupancy
+    // that hides the latency of the rest.  A slot of a multiple of 32 words
+    // would put the same word of every lane's slot in one LDS bank, so such a
+    // slot gives up 4 words.
+    for (int64_t k : {3, 4, 6, 8, 10, 12, 14, 16}) {
         int64_t Pk = (static_cast<int64_t>(c->lds_bytes) / (k * kWave * 4) - 4) & ~int64_t(3);
         if ((Pk + 4) % 32 == 0) Pk -= 4;
         if (Pk > 0 && Pk < b->max_n && std::find(lds_c.begin(), lds_c.end(), Pk) == lds_c.end()) lds_c.push_back(Pk);
@@ -1402,6 +1404,9 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         for (int knob = 1; knob <= 4 && !rc; ++knob) {
             for (int64_t val : *lists[knob]) {
                 if (val == kc[knob]) continue;
+                // the LDS first pass needs whole memories in their slots;
+                // with a smaller slot it is the plain first pass, timed already
+                if (knob == 1 && kind == 1 && val < static_cast<int64_t>(b->max_n)) continue;
                 if (knob == 1 && val > 0 &&
                     static_cast<uint64_t>(kWave) * slot_words(static_cast<uint32_t>(val), b->max_n, b->max_ell) * 4 >
                         static_cast<uint64_t>(c->lds_bytes)) continue;

@@ -82,6 +82,7 @@ __device__ __forceinline__ const gi32 *gptr(const int32_t *p) { return (const gi
 
 struct GlobalMem {                       // every word in HBM
     static constexpr bool kLds = false;
+    static constexpr bool kColdIO = false;
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
     __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
@@ -105,6 +106,7 @@ struct GlobalMem {                       // every word in HBM
 
 struct LdsMem {                          // whole memory in the lane's LDS slot (n <= P)
     static constexpr bool kLds = true;
+    static constexpr bool kColdIO = false;
     uint32_t base;                       // word index of the slot in rasp_lds
     uint32_t spare;                      // word index of the slot's spare word
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
@@ -125,6 +127,10 @@ struct LdsMem {                          // whole memory in the lane's LDS slot 
 
 struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     static constexpr bool kLds = false;
+    // split slots serve memories larger than LDS holds whole, typically
+    // array programs whose reads and prints come in bursts at the start and
+    // end: their tape reads and output stores are laid out of line
+    static constexpr bool kColdIO = true;
     uint32_t base, P;
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const
@@ -293,6 +299,10 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         int32_t w = a;
         if (Tape::kLds) {
             w = rd_ok ? tv : a;                                // loaded one step ahead
+        } else if (Mem::kColdIO) {
+            if (__builtin_expect(__ballot(rd_ok) != 0, 0)) {
+                if (rd_ok) w = tape.ld(u0);
+            }
         } else if (rd_ok) {
             w = tape.ld(u0);
         }
@@ -310,7 +320,11 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         na = op == 1u ? static_cast<uint32_t>(jcur) : na;
         a = static_cast<int32_t>(na);
         const bool app = (op == 7u) & (y0 < s);
-        out.st(y0, d, app);
+        if (Mem::kColdIO) {
+            if (__builtin_expect(__ballot(app) != 0, 0)) out.st(y0, d, app);
+        } else {
+            out.st(y0, d, app);
+        }
         y0 += app ? 1u : 0u;
         i = ni;
         p = np;

@@ -39,3 +39,39 @@ def test_served_results_equal_standalone_runs():
             assert np.array_equal(np.asarray(q.result[k])[idx], getattr(want, k)), (q.rid, k)
     alone.close()
     ctx.close()
+
+
+def test_beaver_search_on_the_served_path_matches_the_oracle():
+    """App. B's search on the GPU (L = 120, all arrays zero, w = 29): the
+    reported busiest beavers, halting count and tau_h decades equal what the
+    oracle gives on the same sampled programs."""
+    import torch
+    from paper_2604_12902_amd import rasp as R, search, workloads as W
+    assert torch.cuda.is_available()
+    seed, rounds, batch, L, w, tau_max, keep = 7, 2, 3000, 120, 29, 20000, 8
+    print("case: beaver search rounds=%d batch=%d L=%d w=%d tau_max=%d" % (rounds, batch, L, w, tau_max),
+          flush=True)
+    ctx = R.Context(1 << 30)
+    res = search.search(serving.RaspExecutor(ctx), rounds=rounds, batch=batch, L=L, w=w,
+                        tau_max=tau_max, keep=keep, seed=seed, cap_bytes=(1 << 30) - (64 << 20))
+    ctx.close()
+    halting, dec, run = [], {}, 0
+    for r in range(rounds):
+        progs, idx = [], []
+        for v in range(batch):
+            words = search.lower(search.program_source(seed, r, batch, v, L))
+            if words is not None:
+                progs.append(words)
+                idx.append(v)
+        b = W.from_programs(W.ISA_WORD, progs, search.BB_N, None, ell=search.BB_ELL, s=search.BB_S)
+        st = oracle.run(b, tau_max, w=w, threads=8)
+        run += len(idx)
+        for k, v in enumerate(idx):
+            if st.status[k] == oracle.HALTED:
+                t = int(st.steps[k])
+                halting.append((t, r, v))
+                d = int(np.floor(np.log10(t))) if t > 0 else -1
+                dec[d] = dec.get(d, 0) + 1
+    assert res.programs == run and res.halted == len(halting)
+    assert [(t, r, v) for t, r, v, _ in res.best] == sorted(halting, key=lambda e: (-e[0], e[1], e[2]))[:keep]
+    assert res.decades == dec

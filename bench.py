@@ -457,7 +457,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
             "kernel": dom, "kernel_ms": round(dom_ms, 4), "algorithmic_bytes": int(algo),
-            "per_unit": unit_note}
+            "per_unit": unit_note,
+            # the whole path: retired steps/s x algorithmic bytes per step against the peak
+            "path_frac": round(head["value"] * bstep / (HBM_PEAK_GBS * 1e9), 5)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -25,6 +25,7 @@ Workloads (sizes of the stated populations):
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -58,9 +59,13 @@ def parse():
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
     ap.add_argument("--first-pass-kind", type=int, default=None, choices=[0, 1])
-    ap.add_argument("--inflight", type=int, default=1,
-                    help="also time the persistent schedule with this many batches in flight "
-                         "(one context and stream each); 1: skip")
+    ap.add_argument("--inflight", type=int, default=2,
+                    help="the headline times the persistent schedule with this many batches in "
+                         "flight, one context and stream each (1: one batch at a time; the "
+                         "one-batch run is always timed and reported as single_batch)")
+    ap.add_argument("--inflight-cus", choices=["shared", "split"], default="split",
+                    help="with --inflight N: all contexts share every CU, or each context's stream "
+                         "gets its own contiguous 1/N of them")
     ap.add_argument("--lazy", action="store_true",
                     help="build c0 inside the run (RASP_DESC_LAZY) instead of in rasp_load_batch")
     ap.add_argument("--no-autotune", action="store_true",
@@ -198,8 +203,29 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
     checked against the oracle.  Returns throughput and per-batch latency
     (load issued to outputs fetched)."""
     n = args.inflight
-    ctxs = [ctx] + [R.Context(arena) for _ in range(n - 1)]
-    for c in ctxs[1:]:
+    streams = []
+    if args.inflight_cus == "split":
+        # each context's stream runs on its own contiguous 1/n of the compute
+        # units (a CU mask), so one batch's latency-bound tail does not share
+        # SIMDs with the next batch's bandwidth-bound load and first pass
+        hip = ctypes.CDLL("libamdhip64.so")
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        for k in range(n):
+            bits = [c for c in range(cus) if c * n // cus == k]
+            mask = (ctypes.c_uint32 * ((cus + 31) // 32))()
+            for c in bits:
+                mask[c // 32] |= 1 << (c % 32)
+            h = ctypes.c_void_p()
+            rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), len(mask), mask)
+            if rc != 0:
+                raise SystemExit("bench: hipExtStreamCreateWithCUMask failed (%d)" % rc)
+            streams.append(h)
+        ctxs = [R.Context(arena, stream=h.value) for h in streams]
+    else:
+        ctxs = [ctx] + [R.Context(arena) for _ in range(n - 1)]
+    for c in ctxs:
+        if c is ctx:
+            continue
         for o in (R.RASP_OPT_SCHEDULE, R.RASP_OPT_LDS_WORDS, R.RASP_OPT_FIRST_PASS, R.RASP_OPT_EPOCH,
                   R.RASP_OPT_WAVES_PER_CU, R.RASP_OPT_FIRST_PASS_KIND):
             c.set(o, ctx.get(o))
@@ -238,10 +264,22 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
 
     run(max(args.warmup, n))
     torch.cuda.synchronize()
+    for c in ctxs:
+        c.set(R.RASP_OPT_PROFILE, 1)
+        R.rasp_kernel_times(c.handle)                   # reset
+    torch.cuda.synchronize()
     t_start = time.perf_counter()
     lat = run(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    # kernel times of the timed region, summed over the contexts (HIP events
+    # on each context's own stream)
+    kt = {}
+    for c in ctxs:
+        for k, (ms, cnt) in R.rasp_kernel_times(c.handle).items():
+            a, b = kt.get(k, (0.0, 0))
+            kt[k] = (a + ms, b + cnt)
+        c.set(R.RASP_OPT_PROFILE, 0)
     if args.verify != "none":
         for c in range(n):
             for k in ("status", "steps", "i", "a", "u0", "y0"):
@@ -250,14 +288,23 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                     raise SystemExit("bench: NOT bit-exact with %d batches in flight: %s" % (n, k))
             if not np.array_equal(outs[c]["y"].cpu().numpy(), ref.Y):
                 raise SystemExit("bench: NOT bit-exact with %d batches in flight: output words" % n)
-    for c in ctxs[1:]:
-        c.close()
-    res = {"batches_in_flight": n, "value": total_steps / (wall / args.steps),
+    for c in ctxs:
+        if c is not ctx:
+            c.close()
+    for h in streams:
+        hip.hipStreamDestroy(h)
+    knobs = dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
+                 first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
+                 waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
+                 first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=args.lazy,
+                 batches_in_flight=n, cu_partition=args.inflight_cus)
+    res = {"batches_in_flight": n, "cus": args.inflight_cus, "value": total_steps / (wall / args.steps),
            "ms_per_step": 1e3 * wall / args.steps,
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-           "bit_exact": args.verify != "none"}
-    print("bench: inflight=%d %.3f ms/step  %.3e steps/s  batch latency p50 %.3f p99 %.3f ms" % (
-        n, res["ms_per_step"], res["value"], res["p50_ms"], res["p99_ms"]), flush=True)
+           "bit_exact": args.verify != "none", "kernels": kt, "knobs": knobs}
+    print("bench: inflight=%d %.3f ms/step  %.3e steps/s  batch latency p50 %.3f p99 %.3f ms  kernels %s" % (
+        n, res["ms_per_step"], res["value"], res["p50_ms"], res["p99_ms"],
+        {k: "%.3f ms x%d" % (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1]}), flush=True)
     return res
 
 
@@ -416,10 +463,13 @@ def main():
 
     inflight = None
     if args.inflight > 1:
+        configure(R.RASP_SCHED_PERSISTENT)              # the knobs the contexts copy
         inflight = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
                                   total_steps)
 
-    head = results["persistent"]
+    # the headline: the persistent schedule with the batches in flight the
+    # run was asked for (one: results["persistent"])
+    head = inflight if inflight is not None else results["persistent"]
     kt = head["kernels"]
     # dominant kernel of the headline schedule: largest total time
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
@@ -479,14 +529,17 @@ def main():
                    "first_pass": fp_pass, "lds_words": head["knobs"]["lds_words"],
                    "c0_in_run": args.lazy, "autotuned": tuned is not None,
                    "epoch": head["knobs"]["epoch"], "waves_per_cu": head["knobs"]["waves_per_cu"],
-                   "first_pass_kind": head["knobs"]["first_pass_kind"]},
+                   "first_pass_kind": head["knobs"]["first_pass_kind"],
+                   "batches_in_flight": args.inflight if inflight is not None else 1,
+                   "cu_partition": args.inflight_cus if inflight is not None else "shared"},
+        # p50/p99: per-batch latency, load issued to outputs fetched
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "single_batch": {k: results["persistent"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms")},
         "plain": ({k: results["plain"][k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms")}
                   if "plain" in results else None),
         "bit_exact": args.verify,
         "roofline": roof,
         "cpu_baseline": cpu,
-        "inflight": inflight,
     }
     if args.json_extra:
         with open(args.json_extra, "w") as f:

@@ -365,6 +365,8 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x, uint32_t L)
            bcast(static_cast<uint32_t>(x), L);
 }
 
+constexpr int kPackGroup = 4;            // machines whose loads are in flight together
+
 __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restrict__ prog,
                                               const uint64_t *__restrict__ prog_off,
                                               const int32_t *__restrict__ tape,
@@ -387,6 +389,44 @@ __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restr
             b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0; b.status[v] = 0;
         }
         const uint32_t cnt = static_cast<uint32_t>(b.N - g < kWave ? b.N - g : kWave);
+        // Every machine of the wave one row wide (n <= 256 words, l and s <=
+        // 64, program 16-byte aligned and a multiple of 4 words): the loads of
+        // kPackGroup machines go out together -- each at an address clamped
+        // into its program or tape, the words past the end replaced by zeros
+        // afterwards -- so a group costs one memory round trip instead of one
+        // per machine.
+        const bool row = v >= b.N || (n <= 4u * kWave && ell <= kWave && s <= kWave &&
+                                      (p0 & 3u) == 0 && (plen & 3u) == 0);
+        if (__ballot(!row) == 0) {
+            const uint32_t k = 4u * lane;
+            for (uint32_t L0 = 0; L0 < cnt; L0 += kPackGroup) {
+                int4 x[kPackGroup];
+                int32_t y[kPackGroup];
+#pragma unroll
+                for (int u = 0; u < kPackGroup; ++u) {
+                    const uint32_t L = L0 + u < cnt ? L0 + u : cnt - 1;
+                    const uint64_t P0 = bcast64(p0, L), T0 = bcast64(t0, L);
+                    const uint32_t PL = bcast(plen, L), TL = bcast(tlen, L);
+                    x[u] = int4{0, 0, 0, 0};
+                    y[u] = 0;
+                    if (PL > 0) x[u] = *reinterpret_cast<const int4 *>(prog + P0 + (k < PL ? k : PL - 4u));
+                    if (TL > 0) y[u] = tape[T0 + (lane < TL ? lane : TL - 1u)];
+                }
+#pragma unroll
+                for (int u = 0; u < kPackGroup; ++u) {
+                    const uint32_t L = L0 + u;
+                    if (L >= cnt) break;
+                    const uint64_t MO = bcast64(mo, L), TO = bcast64(to, L), YO = bcast64(yo, L);
+                    const uint32_t PL = bcast(plen, L), TL = bcast(tlen, L);
+                    const uint32_t NN = bcast(n, L), EL = bcast(ell, L), SS = bcast(s, L);
+                    const int4 w = k < PL ? x[u] : int4{0, 0, 0, 0};
+                    if (k < NN) *reinterpret_cast<int4 *>(b.M + MO + k) = w;     // slices are padded to 4 words
+                    if (lane < EL) b.T[TO + lane] = lane < TL ? y[u] : 0;
+                    if (lane < SS) b.Y[YO + lane] = 0;
+                }
+            }
+            continue;
+        }
         for (uint32_t L = 0; L < cnt; ++L) {
             const uint64_t P0 = bcast64(p0, L), MO = bcast64(mo, L);
             const uint32_t PL = bcast(plen, L), NN = bcast(n, L);

@@ -29,6 +29,7 @@ import ctypes
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -59,10 +60,11 @@ def parse():
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
     ap.add_argument("--first-pass-kind", type=int, default=None, choices=[0, 1])
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=0,
                     help="the headline times the persistent schedule with this many batches in "
-                         "flight, one context and stream each (1: one batch at a time; the "
-                         "one-batch run is always timed and reported as single_batch)")
+                         "flight, one context, stream and host thread each (1: one batch at a "
+                         "time; 0: the best of 1, 2 and 4 in short untimed trials); the "
+                         "one-batch run is always timed and reported as single_batch")
     ap.add_argument("--inflight-cus", choices=["shared", "split"], default="split",
                     help="with --inflight N: all contexts share every CU, or each context's stream "
                          "gets its own contiguous 1/N of them")
@@ -189,20 +191,28 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
     return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs)
 
 
+# batches in flight tried: each in-flight stream carries its own CU mask and so
+# needs a hardware queue of its own; HIP gives a process 4 by default
+INFLIGHT_CANDIDATES = (1, 2, 4)
+
+
 def arena_inflight(fp):
     """Arena of a context that only loads, runs and fetches (no autotune snapshot)."""
     return int(fp * 1.25) + (256 << 20)
 
 
-def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_steps):
-    """The persistent schedule with `args.inflight` batches in flight, one per
-    context (each context has its own stream): batch k is loaded and launched
-    before batch k-1 is fetched, so the load and first pass of one batch run
-    beside the long tail of the one before.  Every batch does the whole work
-    (load, run, fetch); the outputs of the last batch of each context are
-    checked against the oracle.  Returns throughput and per-batch latency
-    (load issued to outputs fetched)."""
-    n = args.inflight
+def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_steps, n, steps=None,
+                   warmup=None, verify=True, quiet=False):
+    """The persistent schedule with `n` batches in flight: one
+    context per batch in flight, each with its own stream and its own host
+    thread that loads, runs and fetches its share of the batches one after
+    another, so the load and first pass of one batch run beside the long tail
+    of another.  Every batch does the whole work (load, run, fetch); the
+    outputs of the last batch of each context are checked against the
+    oracle.  Returns throughput and per-batch latency (load issued to outputs
+    fetched)."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     streams = []
     if args.inflight_cus == "split":
         # each context's stream runs on its own contiguous 1/n of the compute
@@ -243,33 +253,40 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                     y=torch.empty(ny, dtype=torch.int32, device=dev))
     outs = [new_outs() for _ in range(n)]
 
-    def run(steps):
-        pending, lat = [], []
-        for k in range(steps):
-            c = k % n
-            t_issue = time.perf_counter()
-            h = R.rasp_load_batch(ctxs[c].handle, desc)
-            R.rasp_run(ctxs[c].handle, h, budget)
-            pending.append((c, h, t_issue))
-            if len(pending) == n:
-                c0, h0, t0 = pending.pop(0)
-                R.rasp_fetch_outputs_into(ctxs[c0].handle, h0, outs[c0], device=True)
-                R.rasp_free_batch(ctxs[c0].handle, h0)
-                lat.append(time.perf_counter() - t0)
-        for c0, h0, t0 in pending:
-            R.rasp_fetch_outputs_into(ctxs[c0].handle, h0, outs[c0], device=True)
-            R.rasp_free_batch(ctxs[c0].handle, h0)
-            lat.append(time.perf_counter() - t0)
-        return np.array(lat)
+    def drive(c, count, lat, errors):
+        # one host thread per context: load, run, fetch, free, one batch after
+        # another (the library's calls release the interpreter lock)
+        try:
+            for _ in range(count):
+                t_issue = time.perf_counter()
+                h = R.rasp_load_batch(ctxs[c].handle, desc)
+                R.rasp_run(ctxs[c].handle, h, budget)
+                R.rasp_fetch_outputs_into(ctxs[c].handle, h, outs[c], device=True)
+                R.rasp_free_batch(ctxs[c].handle, h)
+                lat.append(time.perf_counter() - t_issue)
+        except Exception as e:                          # re-raised by run()
+            errors.append(e)
 
-    run(max(args.warmup, n))
+    def run(steps):
+        lat, errors = [[] for _ in range(n)], []
+        threads = [threading.Thread(target=drive, args=(c, steps // n + (c < steps % n), lat[c], errors))
+                   for c in range(n)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+        return np.array([x for part in lat for x in part])
+
+    run(max(warmup, n))
     torch.cuda.synchronize()
     for c in ctxs:
         c.set(R.RASP_OPT_PROFILE, 1)
         R.rasp_kernel_times(c.handle)                   # reset
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    lat = run(args.steps)
+    lat = run(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     # kernel times of the timed region, summed over the contexts (HIP events
@@ -280,7 +297,7 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
             a, b = kt.get(k, (0.0, 0))
             kt[k] = (a + ms, b + cnt)
         c.set(R.RASP_OPT_PROFILE, 0)
-    if args.verify != "none":
+    if verify and args.verify != "none":
         for c in range(n):
             for k in ("status", "steps", "i", "a", "u0", "y0"):
                 got = outs[c][k].cpu().numpy()
@@ -298,10 +315,12 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                  waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
                  first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=args.lazy,
                  batches_in_flight=n, cu_partition=args.inflight_cus)
-    res = {"batches_in_flight": n, "cus": args.inflight_cus, "value": total_steps / (wall / args.steps),
-           "ms_per_step": 1e3 * wall / args.steps,
+    res = {"batches_in_flight": n, "cus": args.inflight_cus, "value": total_steps / (wall / steps),
+           "ms_per_step": 1e3 * wall / steps,
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
            "bit_exact": args.verify != "none", "kernels": kt, "knobs": knobs}
+    if quiet:
+        return res
     print("bench: inflight=%d %.3f ms/step  %.3e steps/s  batch latency p50 %.3f p99 %.3f ms  kernels %s" % (
         n, res["ms_per_step"], res["value"], res["p50_ms"], res["p99_ms"],
         {k: "%.3f ms x%d" % (v[0] / max(1, v[1]), v[1]) for k, v in kt.items() if v[1]}), flush=True)
@@ -462,10 +481,27 @@ def main():
             flush=True)
 
     inflight = None
-    if args.inflight > 1:
-        configure(R.RASP_SCHED_PERSISTENT)              # the knobs the contexts copy
+    n_flight = args.inflight
+    configure(R.RASP_SCHED_PERSISTENT)                  # the knobs the contexts copy
+    if n_flight == 0:
+        # batches in flight chosen like the other knobs: a short untimed trial
+        # of each candidate (2n batches after n warm-up ones); a larger count
+        # must be at least 3% faster
+        best = None
+        for cand in INFLIGHT_CANDIDATES:
+            if cand == 1:
+                rate = results["persistent"]["value"]
+            else:
+                rate = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
+                                      total_steps, cand, steps=2 * cand, warmup=cand, verify=False,
+                                      quiet=True)["value"]
+            print("bench: trial %d in flight: %.3e steps/s" % (cand, rate), flush=True)
+            if best is None or rate > best[1] / 0.97:
+                best = (cand, rate)
+        n_flight = best[0]
+    if n_flight > 1:
         inflight = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
-                                  total_steps)
+                                  total_steps, n_flight)
 
     # the headline: the persistent schedule with the batches in flight the
     # run was asked for (one: results["persistent"])
@@ -530,7 +566,7 @@ def main():
                    "c0_in_run": args.lazy, "autotuned": tuned is not None,
                    "epoch": head["knobs"]["epoch"], "waves_per_cu": head["knobs"]["waves_per_cu"],
                    "first_pass_kind": head["knobs"]["first_pass_kind"],
-                   "batches_in_flight": args.inflight if inflight is not None else 1,
+                   "batches_in_flight": n_flight if inflight is not None else 1,
                    "cu_partition": args.inflight_cus if inflight is not None else "shared"},
         # p50/p99: per-batch latency, load issued to outputs fetched
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],

@@ -556,3 +556,53 @@ def test_fetch_into_device_buffers(ctx, rasp):
     assert np.array_equal(part["steps"].cpu().numpy().view(np.uint64), np.asarray(host["steps"]))
     assert np.array_equal(part["a"].cpu().numpy(), np.asarray(host["a"]))
     ctx.free(h)
+
+
+def test_contexts_on_their_own_threads_and_cu_shares(rasp):
+    """What the benchmark's batches in flight rely on: four contexts, each on
+    a stream restricted to its own quarter of the CUs and driven by its own
+    host thread, load, run and fetch different batches at the same time, and
+    every result is bit-exact."""
+    import ctypes
+    import threading
+    import torch
+    R = rasp
+    hip = ctypes.CDLL("libamdhip64.so")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 4
+    streams, ctxs = [], []
+    for k in range(n):
+        mask = (ctypes.c_uint32 * ((cus + 31) // 32))()
+        for c in range(cus):
+            if c * n // cus == k:
+                mask[c // 32] |= 1 << (c % 32)
+        h = ctypes.c_void_p()
+        assert hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), len(mask), mask) == 0
+        streams.append(h)
+        ctxs.append(R.Context(256 << 20, stream=h.value))
+    batches = [W.config1(seed=40 + k, num_vms=3000) if k % 2 == 0 else
+               W.config3(num_vms=3000, seed=50 + k, budget=3000) for k in range(n)]
+    print("case: %d contexts on CU quarters, 3 rounds each" % n, flush=True)
+    got, errors = [[] for _ in range(n)], []
+
+    def drive(k):
+        try:
+            for _ in range(3):
+                got[k].append(run_gpu(ctxs[k], batches[k], batches[k].budget))
+        except Exception as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=drive, args=(k,)) for k in range(n)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for c in ctxs:
+        c.close()
+    for h in streams:
+        hip.hipStreamDestroy(h)
+    assert not errors, errors
+    for k in range(n):
+        want = oracle.run(batches[k], batches[k].budget, threads=4)
+        for out in got[k]:
+            compare(out, want)

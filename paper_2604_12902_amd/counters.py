@@ -8,8 +8,9 @@ per dispatch times that scale is its traffic.
 
 The result is recorded in profiles/<workload>_<kernel>_traffic.json under the
 scheduling knobs of the profiled run (the traffic of a launch depends on
-them) together with the SHA-256 of the kernel source; bench.py reports it
-only for a run with the same knobs and the same kernels.
+them) together with the SHA-256 of the kernel source's code (comments and
+whitespace aside); bench.py reports it only for a run with the same knobs and
+the same kernel code.
 
 usage: python -m paper_2604_12902_amd.counters FETCH_DIR WRITE_DIR BYTES KERNEL_SUBSTRING OUT_JSON KNOBS_JSON
 """
@@ -17,15 +18,24 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sqlite3
 import sys
 
 KERNELS_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "rasp_kernels.hip")
 
 
+def code_sha256(text: str) -> str:
+    """SHA-256 of C++ source with comments removed and whitespace collapsed,
+    so that a record outlives edits to comments but not to code."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+
+
 def kernels_sha256() -> str:
-    with open(KERNELS_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    with open(KERNELS_SRC, encoding="utf-8") as f:
+        return code_sha256(f.read())
 
 
 def per_dispatch(d, counter):

@@ -69,7 +69,9 @@ __device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t 
 // memory accessors.  kLds: every word of the machine is in its LDS slot, so
 // the data word is read unconditionally and a store that does not happen is
 // redirected to the slot's spare word (no branch).  Otherwise reads and
-// stores that would touch HBM are predicated.
+// stores that would touch HBM are predicated; a split slot first tests, once
+// per transition for the whole wave, whether any lane touches HBM at all.
+// step() does one transition's memory traffic in program order.
 // ---------------------------------------------------------------------------
 
 extern __shared__ int32_t rasp_lds[];
@@ -202,18 +204,6 @@ struct Regs {
     uint32_t n, ell, s;
 };
 
-// Advance one machine by at most `limit` transitions.  Returns the number
-// applied; `halted` says whether the machine now sits on a fixed point;
-//
-// Software-pipelined: the words of the next instruction are loaded together
-// with the data word of the current one (after the current store, so that a
-// program that rewrites its next instruction sees the new word), leaving one
-// memory round trip per transition; the loop has a single exit.
-// POW2 (n a power of two): v mod n = v & (n-1) for every int32 v, and
-// (i + k) mod n = (p + k) mod n across the int32 wrap, so positions need no
-// division and no special case.  Otherwise the common case -- operand word in
-// [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code and
-// everything else takes one branch that lanes skip when none needs it.
 // the fixed-point predicate of the current configuration (F of Sec. 1.1/2.1):
 // unknown opcode, READ with the tape used up, or a taken jump onto itself
 template <int ISA>
@@ -230,6 +220,19 @@ __device__ __forceinline__ bool stuck(uint32_t op, int32_t j, int32_t a, int32_t
     return !valid | ((op == 6u) & (u0 >= ell)) | (taken & (j == i));
 }
 
+// Advance one machine by at most `limit` transitions.  Returns the number
+// applied; `halted` says whether the machine now sits on a fixed point.
+//
+// Software-pipelined: the words of the next instruction are loaded together
+// with the data word of the current one (after the current store, so that a
+// program that rewrites its next instruction sees the new word), leaving one
+// memory round trip per transition; the loop has a single exit.
+// POW2 (n a power of two): v mod n = v & (n-1) for every int32 v, and
+// (i + k) mod n = (p + k) mod n across the int32 wrap, so positions need no
+// division and no special case.  Otherwise the common case -- operand word in
+// [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code and
+// the general positions are computed out of line, behind one wave-uniform
+// branch that is not taken while no lane needs them.
 // WM: words narrower than 32 bits (ws = 32 - w; POW2 then also needs n <= 2^w).
 // A tape staged in LDS is read one step ahead: the word at u0 is loaded with
 // the next instruction's words, so a READ costs no extra round trip.

@@ -1,0 +1,38 @@
+"""The traffic records bench.py reports: keyed by the scheduling knobs and
+by the kernel source's code (comments and whitespace aside)."""
+import json
+
+from paper_2604_12902_amd import counters
+
+
+def test_code_hash_ignores_comments_and_whitespace_only():
+    a = "int f(int x) {  // doubles\n    return 2 * x; /* the\n result */\n}\n"
+    b = "int f(int x)\n{\n  return 2 * x;\n}  // edited comment\n"
+    c = "int f(int x) { return 3 * x; }"
+    assert counters.code_sha256(a) == counters.code_sha256(b)
+    assert counters.code_sha256(a) != counters.code_sha256(c)
+
+
+def test_lookup_needs_the_same_knobs_and_kernel_code(tmp_path):
+    knobs = {"schedule": 2, "lds_words": 256, "epoch": 256}
+    path = tmp_path / "w_k_traffic.json"
+    path.write_text(json.dumps({"kernels_sha256": counters.kernels_sha256(),
+                                "runs": [{"knobs": knobs, "bytes_per_launch": 123.0}]}))
+    assert counters.lookup(str(path), knobs) == 123.0
+    assert counters.lookup(str(path), dict(knobs, epoch=1024)) is None
+    path.write_text(json.dumps({"kernels_sha256": "0" * 64,
+                                "runs": [{"knobs": knobs, "bytes_per_launch": 123.0}]}))
+    assert counters.lookup(str(path), knobs) is None
+    assert counters.lookup(str(tmp_path / "missing.json"), knobs) is None
+
+
+def test_committed_records_match_the_current_kernels():
+    """The plain-scale records under profiles/ were taken on the kernel code
+    in the tree (otherwise bench.py would report traffic as null)."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for k in ("persistent", "pack", "plain"):
+        with open(os.path.join(root, "profiles", "plain-scale_%s_traffic.json" % k)) as f:
+            rec = json.load(f)
+        assert rec["kernels_sha256"] == counters.kernels_sha256(), k
+        assert rec["runs"]

@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--loads", default="0.5,0.8,1.0", help="serve: offered load, fractions of capacity")
     ap.add_argument("--cap-gb", type=float, default=200.0, help="serve: arena footprint cap")
     ap.add_argument("--serve-epoch", type=int, default=4096, help="serve: transitions per epoch")
+    ap.add_argument("--serve-partitions", type=int, default=0,
+                    help="serve: servers, each with its own context on its own CU share (0: one "
+                         "or four, whichever serves the closed loop faster)")
     ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-schedule comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -135,21 +138,55 @@ def serve_bench(args):
         len(reqs), time.time() - t0, sum(q.size for q in reqs)), flush=True)
     free, _ = torch.cuda.mem_get_info()
     cap = int(min(args.cap_gb * 1e9, 0.85 * free))
-    ctx = R.Context(cap + (256 << 20))
-    ex = serving.RaspExecutor(ctx)
+    state = {}
+
+    def open_partitions(k):
+        """k servers: one context each (k > 1: on its own CU share), sharing the cap."""
+        close_partitions()
+        if k == 1:
+            state["ctxs"] = [R.Context(cap + (256 << 20))]
+            state["hip"], state["streams"] = None, []
+        else:
+            state["hip"], state["streams"] = masked_streams(torch, k)
+            state["ctxs"] = [R.Context(cap // k + (256 << 20), stream=h.value) for h in state["streams"]]
+        state["k"] = k
+
+    def close_partitions():
+        for c in state.get("ctxs", []):
+            c.close()
+        for h in state.get("streams", []):
+            state["hip"].hipStreamDestroy(h)
+        state.clear()
 
     def run(qps):
         for q, a in zip(reqs, base_arrivals):
             q.arrival = 0.0 if qps is None else a / qps
             q.result = None
-        st = serving.Server(ex, cap, epoch=args.serve_epoch).serve(reqs)
-        return st
+        exs = [serving.RaspExecutor(c) for c in state["ctxs"]]
+        if len(exs) == 1:
+            return serving.Server(exs[0], cap, epoch=args.serve_epoch).serve(reqs)
+        return serving.serve_partitioned(exs, reqs, cap, epoch=args.serve_epoch)
 
-    run(None)                                           # warm-up
+    # partitions: one server on the whole chip, or (chosen when the closed
+    # loop is at least 3% faster) one per CU share; each closed loop after a
+    # warm-up pass
+    closed = None
+    for k in ([1, SERVE_PARTITIONS] if args.serve_partitions == 0 else [args.serve_partitions]):
+        open_partitions(k)
+        run(None)                                       # warm-up
+        st = run(None)
+        print("serve: %d partition(s): closed loop %.3f s, %.1f requests/s, %.3e steps/s" % (
+            k, st.wall_s, st.requests / st.wall_s, st.steps_per_s), flush=True)
+        if closed is None or st.steps_per_s > closed[1].steps_per_s / 0.97:
+            closed = (k, st)
+    if state["k"] != closed[0]:
+        open_partitions(closed[0])
+    parts, closed = closed
+    # the results checked below are those of the chosen configuration
     closed = run(None)
     cap_qps = closed.requests / closed.wall_s
-    print("serve: closed loop %.3f s, %.1f requests/s, %.3e steps/s" % (
-        closed.wall_s, cap_qps, closed.steps_per_s), flush=True)
+    print("serve: closed loop %.3f s, %.1f requests/s, %.3e steps/s (%d partition(s))" % (
+        closed.wall_s, cap_qps, closed.steps_per_s, parts), flush=True)
     # bit-exactness of a sample of every request's machines against the oracle
     for q in reqs[:: max(1, len(reqs) // 6)]:
         idx = np.arange(0, q.batch.N, max(1, q.batch.N // 300))
@@ -166,7 +203,7 @@ def serve_bench(args):
         print("serve: load %.2f qps %.1f: %.3e steps/s  p50 %.1f ms  p99 %.1f ms  epochs %d  "
               "max active %d" % (f, f * cap_qps, st.steps_per_s, st.p50_ms, st.p99_ms, st.epochs,
                                  st.max_active), flush=True)
-    ctx.close()
+    close_partitions()
     head = runs[-1] if runs else None
     line = {"metric": "VM instructions retired/sec (1 GPU), bit-exact; served; p50/p99 request latency",
             "value": head["steps_per_s"] if head else closed.steps_per_s,
@@ -175,7 +212,7 @@ def serve_bench(args):
             "data": "synthetic (seeded Poisson stream of random RASP programs)",
             "config": {"workload": "serving: Poisson stream, %d requests of 1,024-262,144 machines, "
                                    "budgets 4,096-65,536, cap %.1f GB" % (len(reqs), cap / 1e9),
-                       "epoch": args.serve_epoch},
+                       "epoch": args.serve_epoch, "partitions": parts},
             "closed_loop": {"requests_per_s": cap_qps, "steps_per_s": closed.steps_per_s,
                             "p50_ms": closed.p50_ms, "p99_ms": closed.p99_ms},
             "open_loop": runs}
@@ -194,6 +231,27 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
 # batches in flight tried: each in-flight stream carries its own CU mask and so
 # needs a hardware queue of its own; HIP gives a process 4 by default
 INFLIGHT_CANDIDATES = (1, 2, 4)
+SERVE_PARTITIONS = 4
+
+
+def masked_streams(torch, n):
+    """n HIP streams, stream k restricted by a CU mask to the k-th contiguous
+    1/n of the device's compute units.  Returns (the HIP runtime, streams);
+    the caller destroys them with hipStreamDestroy."""
+    hip = ctypes.CDLL("libamdhip64.so")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    streams = []
+    for k in range(n):
+        mask = (ctypes.c_uint32 * ((cus + 31) // 32))()
+        for c in range(cus):
+            if c * n // cus == k:
+                mask[c // 32] |= 1 << (c % 32)
+        h = ctypes.c_void_p()
+        rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), len(mask), mask)
+        if rc != 0:
+            raise SystemExit("bench: hipExtStreamCreateWithCUMask failed (%d)" % rc)
+        streams.append(h)
+    return hip, streams
 
 
 def arena_inflight(fp):
@@ -213,23 +271,12 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
     fetched)."""
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
-    streams = []
+    streams, hip = [], None
     if args.inflight_cus == "split":
         # each context's stream runs on its own contiguous 1/n of the compute
         # units (a CU mask), so one batch's latency-bound tail does not share
-        # SIMDs with the next batch's bandwidth-bound load and first pass
-        hip = ctypes.CDLL("libamdhip64.so")
-        cus = torch.cuda.get_device_properties(0).multi_processor_count
-        for k in range(n):
-            bits = [c for c in range(cus) if c * n // cus == k]
-            mask = (ctypes.c_uint32 * ((cus + 31) // 32))()
-            for c in bits:
-                mask[c // 32] |= 1 << (c % 32)
-            h = ctypes.c_void_p()
-            rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), len(mask), mask)
-            if rc != 0:
-                raise SystemExit("bench: hipExtStreamCreateWithCUMask failed (%d)" % rc)
-            streams.append(h)
+        # SIMDs with the next batch's load and first pass
+        hip, streams = masked_streams(torch, n)
         ctxs = [R.Context(arena, stream=h.value) for h in streams]
     else:
         ctxs = [ctx] + [R.Context(arena) for _ in range(n - 1)]

@@ -146,7 +146,9 @@ class Server:
         self.sleep = sleep
         self.max_batches = max_batches
 
-    def serve(self, requests) -> ServeStats:
+    def serve(self, requests, start=None) -> ServeStats:
+        """Serve `requests`; arrivals count from `start()` (a clock value) when
+        given, else from the end of the footprint pass."""
         pending = sorted(requests, key=lambda q: q.arrival)
         for q in pending:
             if q.batch is None:
@@ -158,7 +160,7 @@ class Server:
         used = 0
         epochs = 0
         max_active = max_fp = 0
-        t0 = self.clock()
+        t0 = self.clock() if start is None else start()
         k = 0
         n_done = 0
         while n_done < len(pending):
@@ -200,7 +202,60 @@ class Server:
                     still.append(q)
             active = still
         wall = self.clock() - t0
+        if not pending:
+            return ServeStats(0, wall, 0, epochs, 0.0, 0.0, 0.0, 0, 0, [])
         lat = np.array([q.latency for q in pending]) * 1e3
         return ServeStats(len(pending), wall, sum(q.steps for q in pending), epochs,
                           float(np.percentile(lat, 50)), float(np.percentile(lat, 99)),
                           float(lat.mean()), max_active, max_fp, lat.tolist())
+
+
+def serve_partitioned(executors, requests, cap_bytes: int, epoch: int = 4096,
+                      clock=time.perf_counter) -> ServeStats:
+    """Serve with one server per executor, each on its own host thread.
+
+    On the device each executor is a context whose stream runs on its own
+    share of the compute units, so the heavy tail of one partition's requests
+    does not hold up another's.  Requests are dealt round-robin in arrival
+    order; each partition gets an equal share of the footprint cap; all
+    partitions count arrivals from one common start.  The merged statistics
+    cover every request: wall time to the last one finished, steps and
+    epochs summed, latency percentiles over all requests.
+    """
+    import threading
+    k = len(executors)
+    reqs = sorted(requests, key=lambda q: q.arrival)
+    parts = [reqs[i::k] for i in range(k)]
+    share = int(cap_bytes) // k
+    barrier = threading.Barrier(k)
+    lock = threading.Lock()
+    shared = {}
+    stats, errors = [None] * k, []
+
+    def start():
+        barrier.wait()
+        with lock:
+            if "t0" not in shared:
+                shared["t0"] = clock()
+        return shared["t0"]
+
+    def run(i):
+        try:
+            stats[i] = Server(executors[i], share, epoch=epoch, clock=clock).serve(parts[i], start=start)
+        except Exception as e:                          # re-raised below
+            errors.append(e)
+            barrier.abort()
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(k)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    if errors:
+        raise errors[0]
+    lat = np.array([q.latency for q in reqs]) * 1e3
+    return ServeStats(len(reqs), max(st.wall_s for st in stats), sum(st.steps for st in stats),
+                      sum(st.epochs for st in stats), float(np.percentile(lat, 50)),
+                      float(np.percentile(lat, 99)), float(lat.mean()),
+                      sum(st.max_active for st in stats), sum(st.max_footprint for st in stats),
+                      lat.tolist())

@@ -107,3 +107,60 @@ def test_poisson_stream_is_seeded():
     assert sizes.min() >= 1024 and sizes.max() <= 262144
     gaps = np.diff([q.arrival for q in serving.poisson_requests(4000, 10.0, seed=5, generate=False)])
     assert 0.09 < gaps.mean() < 0.11
+
+
+class LockedOracleExecutor:
+    """Test double for one partition: oracle states, and a record of the
+    footprint in use (each partition has its own)."""
+
+    def __init__(self, cap):
+        self.cap, self.states, self.fp, self.next = cap, {}, {}, 1
+        self.used = self.max_used = 0
+
+    def footprint(self, batch):
+        return 64 * batch.N + 4 * batch.footprint_words()
+
+    def load(self, batch):
+        h = self.next
+        self.next += 1
+        self.states[h] = oracle.init(batch)
+        self.fp[h] = self.footprint(batch)
+        self.used += self.fp[h]
+        self.max_used = max(self.max_used, self.used)
+        assert self.used <= self.cap
+        return h
+
+    def run(self, handles, budgets):
+        for h, b in zip(handles, budgets):
+            oracle.advance(self.states[h], b)
+
+    def running(self, handles):
+        return np.array([int((self.states[h].status == 0).sum()) for h in handles])
+
+    def fetch(self, h):
+        st = self.states[h]
+        return dict(status=st.status.copy(), steps=st.steps.copy(), i=st.i.copy(), a=st.a.copy(),
+                    u0=st.u0.copy(), y0=st.y0.copy(), y=st.Y.copy(), mem_digest=oracle.digest(st))
+
+    def free(self, h):
+        self.used -= self.fp.pop(h)
+        del self.states[h]
+
+
+def test_partitioned_serving_deals_requests_and_keeps_each_share_of_the_cap():
+    reqs = small_requests(n=18, qps=4000.0)
+    k = 3
+    share = 2 * max(64 * q.batch.N + 4 * q.batch.footprint_words() for q in reqs)
+    exs = [LockedOracleExecutor(share) for _ in range(k)]
+    stats = serving.serve_partitioned(exs, reqs, k * share, epoch=60)
+    assert stats.requests == len(reqs) and stats.p99_ms >= stats.p50_ms > 0
+    for ex in exs:
+        assert 0 < ex.max_used <= share and not ex.states
+    order = sorted(reqs, key=lambda q: q.arrival)
+    for i, q in enumerate(order):
+        want = oracle.run(q.batch, q.budget)
+        for f in ("status", "steps", "i", "a", "u0", "y0"):
+            assert np.array_equal(q.result[f], getattr(want, f)), (q.rid, f)
+        assert np.array_equal(q.result["mem_digest"], oracle.digest(want))
+        assert q.done >= q.admitted >= q.arrival
+    assert stats.steps == sum(int(q.result["steps"].sum()) for q in reqs)

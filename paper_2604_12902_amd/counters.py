@@ -12,7 +12,7 @@ them) together with the SHA-256 of the kernel source's code (comments and
 whitespace aside); bench.py reports it only for a run with the same knobs and
 the same kernel code.
 
-usage: python -m paper_2604_12902_amd.counters FETCH_DIR WRITE_DIR BYTES KERNEL_SUBSTRING OUT_JSON KNOBS_JSON
+usage: python -m paper_2604_12902_amd.counters FETCH_DIR WRITE_DIR BYTES KERNEL_SUBSTRING OUT_JSON KNOBS_JSON [LAST]
 """
 import glob
 import hashlib
@@ -50,12 +50,19 @@ def per_dispatch(d, counter):
     return out
 
 
-def measure(fdir, wdir, nbytes, ksub):
+def measure(fdir, wdir, nbytes, ksub, last=0):
+    """Bytes per launch of the kernels whose name contains `ksub`: the mean
+    over their dispatches, or over the `last` latest ones (a run that times
+    two modes one after the other)."""
     res = {"copy_bytes": nbytes, "kernel": ksub}
+    if last:
+        res["last_dispatches"] = last
     for tag, d, c in (("fetch", fdir, "FETCH_SIZE"), ("write", wdir, "WRITE_SIZE")):
         vals = per_dispatch(d, c)
         copies = [v for (n, _), v in vals.items() if "copyBuffer" in n]
-        kern = [v for (n, _), v in vals.items() if ksub in n]
+        kern = [v for (n, disp), v in sorted(vals.items(), key=lambda e: e[0][1]) if ksub in n]
+        if last:
+            kern = kern[-last:]
         ref = max(copies)
         scale = nbytes / (ref * 1024.0)
         res[tag + "_copy_kib"] = ref
@@ -84,7 +91,8 @@ def lookup(path, knobs):
 def main():
     fdir, wdir, nbytes, ksub, out = sys.argv[1], sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5]
     knobs = json.loads(sys.argv[6])
-    res = measure(fdir, wdir, nbytes, ksub)
+    last = int(sys.argv[7]) if len(sys.argv) > 7 else 0
+    res = measure(fdir, wdir, nbytes, ksub, last)
     res["knobs"] = knobs
     sha = kernels_sha256()
     t = {"kernels_sha256": sha, "runs": []}

@@ -18,9 +18,11 @@
  *   - RASP_E_INVAL leaves the context and all batches exactly as they were;
  *   - RASP_E_DEVICE (a HIP runtime error) is sticky: the context refuses all
  *     further work except rasp_last_error and rasp_destroy;
- *   - a context is driven by one host thread at a time;
- *   - words are 32-bit two's complement (w = 32 of Sec. 3); + and * wrap
- *     mod 2^32.
+ *   - a context is driven by one host thread at a time; different contexts
+ *     (each with its own stream, which may carry a CU mask) may be driven
+ *     from different host threads at the same time;
+ *   - words are w-bit two's complement, w = word_bits of the batch (32 by
+ *     default, the w = 32 of Sec. 3); + and * wrap mod 2^w.
  *
  * Semantics fixed by this library where the paper leaves a choice:
  *   - the program is stored in memory: P occupies M[0 .. 2m), n >= 2m words

@@ -25,7 +25,6 @@ Workloads (sizes of the stated populations):
 from __future__ import annotations
 
 import argparse
-import ctypes
 import json
 import os
 import sys
@@ -145,17 +144,14 @@ def serve_bench(args):
         close_partitions()
         if k == 1:
             state["ctxs"] = [R.Context(cap + (256 << 20))]
-            state["hip"], state["streams"] = None, []
         else:
-            state["hip"], state["streams"] = masked_streams(torch, k)
-            state["ctxs"] = [R.Context(cap // k + (256 << 20), stream=h.value) for h in state["streams"]]
+            cus = torch.cuda.get_device_properties(0).multi_processor_count
+            state["ctxs"] = [R.Context(cap // k + (256 << 20), cus=R.cu_share(i, k, cus)) for i in range(k)]
         state["k"] = k
 
     def close_partitions():
         for c in state.get("ctxs", []):
             c.close()
-        for h in state.get("streams", []):
-            state["hip"].hipStreamDestroy(h)
         state.clear()
 
     def run(qps):
@@ -234,26 +230,6 @@ INFLIGHT_CANDIDATES = (1, 2, 4)
 SERVE_PARTITIONS = 4
 
 
-def masked_streams(torch, n):
-    """n HIP streams, stream k restricted by a CU mask to the k-th contiguous
-    1/n of the device's compute units.  Returns (the HIP runtime, streams);
-    the caller destroys them with hipStreamDestroy."""
-    hip = ctypes.CDLL("libamdhip64.so")
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    streams = []
-    for k in range(n):
-        mask = (ctypes.c_uint32 * ((cus + 31) // 32))()
-        for c in range(cus):
-            if c * n // cus == k:
-                mask[c // 32] |= 1 << (c % 32)
-        h = ctypes.c_void_p()
-        rc = hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), len(mask), mask)
-        if rc != 0:
-            raise SystemExit("bench: hipExtStreamCreateWithCUMask failed (%d)" % rc)
-        streams.append(h)
-    return hip, streams
-
-
 def arena_inflight(fp):
     """Arena of a context that only loads, runs and fetches (no autotune snapshot)."""
     return int(fp * 1.25) + (256 << 20)
@@ -271,13 +247,12 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
     fetched)."""
     steps = args.steps if steps is None else steps
     warmup = args.warmup if warmup is None else warmup
-    streams, hip = [], None
     if args.inflight_cus == "split":
         # each context's stream runs on its own contiguous 1/n of the compute
-        # units (a CU mask), so one batch's latency-bound tail does not share
-        # SIMDs with the next batch's load and first pass
-        hip, streams = masked_streams(torch, n)
-        ctxs = [R.Context(arena, stream=h.value) for h in streams]
+        # units, so one batch's latency-bound tail does not share SIMDs with
+        # the next batch's load and first pass
+        cus = R.rasp_device_info(ctx.handle)["compute_units"]
+        ctxs = [R.Context(arena, cus=R.cu_share(k, n, cus)) for k in range(n)]
     else:
         ctxs = [ctx] + [R.Context(arena) for _ in range(n - 1)]
     for c in ctxs:
@@ -355,8 +330,6 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
     for c in ctxs:
         if c is not ctx:
             c.close()
-    for h in streams:
-        hip.hipStreamDestroy(h)
     knobs = dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
                  first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
                  waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),

@@ -102,6 +102,22 @@ enum { RASP_OUT_DEVICE_PTRS = 1u };   /* every destination is device memory */
 int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes,
                 void *stream);
 
+/*
+ * rasp_create_on_cus: rasp_create on a stream the library creates, restricted
+ * by a CU mask (hipExtStreamCreateWithCUMask) to compute units
+ * [cu_first, cu_first + cu_count) of the device; rasp_destroy destroys it.
+ * Several contexts on disjoint CU ranges, each driven from its own host
+ * thread, run independent batches side by side: one batch's latency-bound
+ * tail then does not share SIMDs with another batch's bandwidth-bound load.
+ * Each such stream takes a hardware queue of its own (HIP gives a process 4
+ * by default).  arena, arena_bytes as for rasp_create.
+ * Errors: INVAL (out == NULL, cu_count == 0, or the range not within the
+ * device's compute units), DEVICE (the runtime refused the mask), and those
+ * of rasp_create.
+ */
+int rasp_create_on_cus(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes,
+                       uint32_t cu_first, uint32_t cu_count);
+
 /* rasp_destroy: wait for queued work, release the context (NULL is a no-op). */
 int rasp_destroy(rasp_ctx *ctx);
 

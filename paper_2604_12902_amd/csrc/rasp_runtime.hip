@@ -849,6 +849,37 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     return RASP_OK;
 }
 
+int rasp_create_on_cus(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, uint32_t cu_first,
+                       uint32_t cu_count)
+{
+    if (!out) return fail(nullptr, RASP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, RASP_E_INVAL, "no HIP device %d", device);
+    hipDeviceProp_t prop;
+    hipError_t e = hipSetDevice(device);
+    if (!e) e = hipGetDeviceProperties(&prop, device);
+    if (e) return fail(nullptr, RASP_E_DEVICE, "device query: %s", hipGetErrorString(e));
+    const uint32_t cus = static_cast<uint32_t>(prop.multiProcessorCount);
+    if (cu_count == 0 || cu_first >= cus || cu_count > cus - cu_first)
+        return fail(nullptr, RASP_E_INVAL, "compute units [%u, %u + %u) are not within the device's %u",
+                    cu_first, cu_first, cu_count, cus);
+    std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+    for (uint32_t k = cu_first; k < cu_first + cu_count; ++k) mask[k / 32] |= 1u << (k % 32);
+    hipStream_t st = nullptr;
+    e = hipExtStreamCreateWithCUMask(&st, static_cast<uint32_t>(mask.size()), mask.data());
+    if (e) return fail(nullptr, RASP_E_DEVICE, "stream on compute units [%u, %u): %s", cu_first,
+                       cu_first + cu_count, hipGetErrorString(e));
+    const int rc = rasp_create(out, device, arena, arena_bytes, st);
+    if (rc) {
+        (void)hipStreamDestroy(st);
+        return rc;
+    }
+    (*out)->own_stream = true;
+    return RASP_OK;
+}
+
 int rasp_destroy(rasp_ctx *c)
 {
     if (!c) return RASP_OK;

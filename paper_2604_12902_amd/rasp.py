@@ -34,7 +34,7 @@ RASP_OPT_PROFILE = 7
 RASP_OPT_FIRST_PASS_KIND = 8
 KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other", "first")
 
-EXPORTED = ("rasp_create", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
+EXPORTED = ("rasp_create", "rasp_create_on_cus", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
             "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH):
     u64, i64, u32, i32 = ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int
     sig = {
         "rasp_create": ([ctypes.POINTER(P), i32, P, u64, P], i32),
+        "rasp_create_on_cus": ([ctypes.POINTER(P), i32, P, u64, u32, u32], i32),
         "rasp_destroy": ([P], i32),
         "rasp_last_error": ([P], ctypes.c_char_p),
         "rasp_batch_footprint": ([ctypes.POINTER(rasp_batch_desc), ctypes.POINTER(u64)], i32),
@@ -170,6 +171,14 @@ def rasp_create(device: int, arena, arena_bytes: int, stream) -> int:
     sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
     rc = _lib.rasp_create(ctypes.byref(out), device, _ptr(arena), arena_bytes, sh)
     _check(rc)
+    return out.value
+
+
+def rasp_create_on_cus(device: int, arena, arena_bytes: int, cu_first: int, cu_count: int) -> int:
+    """A context on its own stream restricted to compute units
+    [cu_first, cu_first + cu_count)."""
+    out = P()
+    _check(_lib.rasp_create_on_cus(ctypes.byref(out), device, _ptr(arena), arena_bytes, cu_first, cu_count))
     return out.value
 
 
@@ -319,12 +328,19 @@ def rasp_kernel_times(ctx) -> dict:
 class Context:
     """Owns a torch-allocated arena and a context on one device."""
 
-    def __init__(self, arena_bytes: int, device: int = 0, stream=None):
+    def __init__(self, arena_bytes: int, device: int = 0, stream=None, cus=None):
+        """cus = (first, count): the context's own stream runs on those compute
+        units only (rasp_create_on_cus); otherwise on `stream`, or a new torch
+        stream."""
         import torch
         self.device = torch.device("cuda", device)
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
-        self.handle = rasp_create(device, self.arena, arena_bytes, self.stream)
+        if cus is not None:
+            self.stream = None
+            self.handle = rasp_create_on_cus(device, self.arena, arena_bytes, int(cus[0]), int(cus[1]))
+        else:
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            self.handle = rasp_create(device, self.arena, arena_bytes, self.stream)
         self._keep = {}
 
     def close(self):
@@ -380,3 +396,9 @@ class Context:
 
     def get(self, option: int) -> int:
         return rasp_get_option(self.handle, option)
+
+
+def cu_share(k: int, n: int, cus: int):
+    """(first, count) of the k-th of n contiguous shares of `cus` compute units."""
+    first = -(-k * cus // n)
+    return first, -(-(k + 1) * cus // n) - first

@@ -75,3 +75,15 @@ def test_binding_constants_match_the_header():
     assert consts["RASP_KERNEL_COUNT"] == len(rasp.KERNEL_NAMES) == len(kinds)
     for n, v in kinds.items():
         assert rasp.KERNEL_NAMES[v] == n[len("RASP_KERNEL_"):].lower(), n
+
+
+def test_cu_shares_tile_the_device():
+    from paper_2604_12902_amd import rasp
+    for cus in (256, 255, 80, 7):
+        for n in (1, 2, 3, 4):
+            shares = [rasp.cu_share(k, n, cus) for k in range(n)]
+            assert shares[0][0] == 0
+            for (f0, c0), (f1, _) in zip(shares, shares[1:]):
+                assert f0 + c0 == f1
+            assert sum(c for _, c in shares) == cus
+            assert max(c for _, c in shares) - min(c for _, c in shares) <= 1

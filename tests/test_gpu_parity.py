@@ -560,26 +560,18 @@ def test_fetch_into_device_buffers(ctx, rasp):
 
 def test_contexts_on_their_own_threads_and_cu_shares(rasp):
     """What the benchmark's batches in flight rely on: four contexts, each on
-    a stream restricted to its own quarter of the CUs and driven by its own
-    host thread, load, run and fetch different batches at the same time, and
-    every result is bit-exact."""
-    import ctypes
+    its own quarter of the CUs (rasp_create_on_cus) and driven by its own host
+    thread, load, run and fetch different batches at the same time, and every
+    result is bit-exact."""
     import threading
-    import torch
     R = rasp
-    hip = ctypes.CDLL("libamdhip64.so")
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
     n = 4
-    streams, ctxs = [], []
-    for k in range(n):
-        mask = (ctypes.c_uint32 * ((cus + 31) // 32))()
-        for c in range(cus):
-            if c * n // cus == k:
-                mask[c // 32] |= 1 << (c % 32)
-        h = ctypes.c_void_p()
-        assert hip.hipExtStreamCreateWithCUMask(ctypes.byref(h), len(mask), mask) == 0
-        streams.append(h)
-        ctxs.append(R.Context(256 << 20, stream=h.value))
+    probe = R.Context(64 << 20)
+    cus = R.rasp_device_info(probe.handle)["compute_units"]
+    probe.close()
+    shares = [R.cu_share(k, n, cus) for k in range(n)]
+    assert sum(c for _, c in shares) == cus and shares[0][0] == 0
+    ctxs = [R.Context(256 << 20, cus=sh) for sh in shares]
     batches = [W.config1(seed=40 + k, num_vms=3000) if k % 2 == 0 else
                W.config3(num_vms=3000, seed=50 + k, budget=3000) for k in range(n)]
     print("case: %d contexts on CU quarters, 3 rounds each" % n, flush=True)
@@ -599,10 +591,19 @@ def test_contexts_on_their_own_threads_and_cu_shares(rasp):
         t.join()
     for c in ctxs:
         c.close()
-    for h in streams:
-        hip.hipStreamDestroy(h)
     assert not errors, errors
     for k in range(n):
         want = oracle.run(batches[k], batches[k].budget, threads=4)
         for out in got[k]:
             compare(out, want)
+
+
+def test_create_on_cus_rejects_ranges_outside_the_device(rasp):
+    R = rasp
+    probe = R.Context(64 << 20)
+    cus = R.rasp_device_info(probe.handle)["compute_units"]
+    probe.close()
+    for first, count in ((0, 0), (cus, 1), (cus - 4, 8)):
+        with pytest.raises(R.RaspError) as e:
+            R.rasp_create_on_cus(0, None, 64 << 20, first, count)
+        assert e.value.code == R.RASP_E_INVAL

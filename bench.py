@@ -59,6 +59,9 @@ def parse():
                     help="serve: servers, each with its own context on its own CU share (0: one "
                          "or four, whichever serves the closed loop faster)")
     ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
+    ap.add_argument("--gen-workers", type=int, default=0,
+                    help="processes generating the fig1 programs (0: up to 16; 1 under a "
+                         "profiler, which would otherwise follow every child process)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-schedule comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", choices=["full", "sample", "none"], default="full")
@@ -98,7 +101,7 @@ def make_batch(args):
     if args.workload == "uneven":
         return W.config3(**kw)
     if args.workload == "fig1":
-        return W.fig1(workers=min(16, os.cpu_count() or 1), **kw)
+        return W.fig1(workers=args.gen_workers or min(16, os.cpu_count() or 1), **kw)
     return W.config4(**kw)
 
 

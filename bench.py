@@ -232,8 +232,7 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
     return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs)
 
 
-# batches in flight tried: each in-flight stream carries its own CU mask and so
-# needs a hardware queue of its own; HIP gives a process 4 by default
+# batches in flight tried (five to eight were slower on every workload tried)
 INFLIGHT_CANDIDATES = (1, 2, 4)
 SERVE_PARTITIONS = 4
 

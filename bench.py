@@ -232,7 +232,7 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
     return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs)
 
 
-# batches in flight tried (five to eight were slower on every workload tried)
+# batches in flight tried (five to eight were slower on plain-scale)
 INFLIGHT_CANDIDATES = (1, 2, 4)
 SERVE_PARTITIONS = 4
 

@@ -229,7 +229,8 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
     for a run with these knobs, or None when there is none or the kernels have
     changed since."""
     from paper_2604_12902_amd import counters
-    return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs)
+    return counters.lookup(os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (workload, kernel)), knobs,
+                           kernel)
 
 
 # batches in flight tried (five to eight were slower on plain-scale)

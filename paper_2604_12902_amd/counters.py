@@ -9,8 +9,8 @@ per dispatch times that scale is its traffic.
 The result is recorded in profiles/<workload>_<kernel>_traffic.json under the
 scheduling knobs of the profiled run (the traffic of a launch depends on
 them) together with the SHA-256 of the kernel source's code (comments and
-whitespace aside); bench.py reports it only for a run with the same knobs and
-the same kernel code.
+whitespace aside); bench.py reports it only for the same kernel code and a
+run that agrees on the knobs that affect that kernel (KNOBS_OF_KERNEL).
 
 usage: python -m paper_2604_12902_amd.counters FETCH_DIR WRITE_DIR BYTES KERNEL_SUBSTRING OUT_JSON KNOBS_JSON [LAST]
 """
@@ -74,16 +74,32 @@ def measure(fdir, wdir, nbytes, ksub, last=0):
     return res
 
 
-def lookup(path, knobs):
-    """Bytes per launch recorded for these knobs and the current kernels, or None."""
+# the knobs that can change the bytes a kernel moves per launch: k_pack runs
+# before any step (only how c0 is built and the CU share matter); the first
+# pass also depends on its length; the persistent kernel on every knob
+KNOBS_OF_KERNEL = {
+    "pack": ("c0_in_run", "batches_in_flight", "cu_partition"),
+    "plain": ("first_pass", "first_pass_kind", "c0_in_run", "batches_in_flight", "cu_partition"),
+}
+
+
+def lookup(path, knobs, kernel=None):
+    """Bytes per launch recorded for the current kernel code and knobs that
+    agree with `knobs` on every knob that affects `kernel` (all knobs when
+    the kernel is not in KNOBS_OF_KERNEL), or None."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
     if t.get("kernels_sha256") != kernels_sha256():
         return None
+    keys = KNOBS_OF_KERNEL.get(kernel)
     for run in t.get("runs", []):
-        if run.get("knobs") == knobs:
+        rk = run.get("knobs", {})
+        if keys is None:
+            if rk == knobs:
+                return run["bytes_per_launch"]
+        elif all(rk.get(k) == knobs.get(k) for k in keys):
             return run["bytes_per_launch"]
     return None
 

@@ -36,3 +36,19 @@ def test_committed_records_match_the_current_kernels():
             rec = json.load(f)
         assert rec["kernels_sha256"] == counters.kernels_sha256(), k
         assert rec["runs"]
+
+
+def test_pack_records_ignore_the_step_loop_knobs(tmp_path):
+    """k_pack runs before any step: its record serves any epoch, slot or
+    first pass, but not another CU share or lazy c0."""
+    rec = {"schedule": 2, "lds_words": 256, "first_pass": 64, "epoch": 256, "waves_per_cu": 16,
+           "first_pass_kind": 0, "c0_in_run": False, "batches_in_flight": 4, "cu_partition": "split"}
+    path = tmp_path / "w_pack_traffic.json"
+    path.write_text(json.dumps({"kernels_sha256": counters.kernels_sha256(),
+                                "runs": [{"knobs": rec, "bytes_per_launch": 7.0}]}))
+    assert counters.lookup(str(path), dict(rec, epoch=64, lds_words=128), "pack") == 7.0
+    assert counters.lookup(str(path), dict(rec, batches_in_flight=2), "pack") is None
+    assert counters.lookup(str(path), dict(rec, c0_in_run=True), "pack") is None
+    assert counters.lookup(str(path), dict(rec, epoch=64), "persistent") is None
+    assert counters.lookup(str(path), dict(rec, epoch=64), "plain") == 7.0
+    assert counters.lookup(str(path), dict(rec, first_pass=16), "plain") is None

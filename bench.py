@@ -105,6 +105,20 @@ def make_batch(args):
     return W.config4(**kw)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name and logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s (%d logical CPUs)" % (name, os.cpu_count() or 0)
+
+
 def bytes_per_step(mix: np.ndarray) -> float:
     """Algorithmic bytes per retired step for a retired-opcode mix:
     8 B fetch (opcode + operand) always; +4 B data read for ADD/SUB/MUL and
@@ -388,6 +402,19 @@ def main():
     bstep = bytes_per_step(mix)
     print("bench: oracle %d threads %.2f s, %d retired steps, %.2f algorithmic B/step" % (
         cores, cpu_s, total_steps, bstep), flush=True)
+    one = None
+    if not args.no_cpu_baseline:
+        # one host thread on every cores-th machine: about the CPU work of the run above
+        sub = batch.subset(np.arange(0, batch.N, cores))
+        t1 = time.time()
+        st1 = oracle.init(sub)
+        oracle.advance(st1, budget, threads=1)
+        one_s = time.time() - t1
+        one = {"value": float(st1.steps.sum()) / one_s,
+               "sample": "every %d-th machine (%d machines, %d retired steps), 1 host thread"
+                         % (cores, sub.N, int(st1.steps.sum()))}
+        print("bench: oracle 1 thread %.2f s on %d machines: %.3e steps/s" % (
+            one_s, sub.N, one["value"]), flush=True)
 
     dev = torch.device("cuda", 0)
     # inputs resident in HBM; c0 is packed by rasp_load_batch (with --lazy the
@@ -580,7 +607,8 @@ def main():
         cpu = {"value": total_steps / cpu_s, "unit": "VM instructions retired/s", "cores": cores,
                "kind": "oracle",
                "sample": "the whole batch (%d machines, %d retired steps), %d host threads, "
-                         "static round-robin striping" % (N, total_steps, cores)}
+                         "static round-robin striping" % (N, total_steps, cores),
+               "one_thread": one, "cpu_model": cpu_model()}
 
     line = {
         "metric": "VM instructions retired/sec (1 GPU), bit-exact; persistent vs plain; p50/p99",

@@ -76,6 +76,13 @@ __device__ __forceinline__ uint32_t advance_pos(int32_t i, uint32_t p, uint32_t 
 
 extern __shared__ int32_t rasp_lds[];
 
+// whether any active lane of the wave has x set (the lane mask of x, ANDed
+// with exec, tested in scalar registers)
+__device__ __forceinline__ bool any_lane(bool x)
+{
+    return __builtin_amdgcn_ballot_w64(x) != 0;
+}
+
 // pointers known to address global memory: loads and stores compile to
 // global_* instructions instead of flat_* ones (which also wait on LDS)
 typedef __attribute__((address_space(1))) int32_t gi32;
@@ -131,7 +138,10 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     static constexpr bool kLds = false;
     // split slots serve memories larger than LDS holds whole, typically
     // array programs whose reads and prints come in bursts at the start and
-    // end: their tape reads and output stores are laid out of line
+    // end: the step loop tests once per transition, for the whole wave,
+    // whether any lane reads the tape, appends an output word, touches a
+    // word at or above P or needs the general positions, and lays all of
+    // that out of line
     static constexpr bool kColdIO = true;
     uint32_t base, P;
     gi32 *M;
@@ -151,26 +161,27 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     {
         if (en) { if (k < P) rasp_lds[base + k] = v; else M[k] = v; }
     }
-    // When no active lane touches a word at or above P in this transition
-    // (the common case once a program and its data sit below P), one
-    // wave-uniform branch selects straight LDS accesses; otherwise each
-    // access picks LDS or HBM per lane.  The spare word after the P memory
-    // words takes the stores of lanes that do not store.
+    // each access picks LDS or HBM per lane
     __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
                                          uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
     {
-        const bool far = ((st_en | need) & (jj >= P)) | (np >= P) | (nq >= P);
-        if (__builtin_expect(__ballot(far) != 0, 0)) {
-            st(jj, w, st_en);
-            d = ld_data(jj, need);
-            o = ld(np);
-            j = ld(nq);
-        } else {
-            rasp_lds[st_en ? base + jj : base + P] = w;
-            d = rasp_lds[base + (jj < P ? jj : 0u)];
-            o = rasp_lds[base + np];
-            j = rasp_lds[base + nq];
-        }
+        st(jj, w, st_en);
+        d = ld_data(jj, need);
+        o = ld(np);
+        j = ld(nq);
+    }
+    // every access of every lane below P: straight LDS accesses.  jx is the
+    // data position of a lane that stores or reads its data word, else 0;
+    // the spare word after the P memory words takes the stores of lanes
+    // that do not store.
+    __device__ __forceinline__ void step_near(uint32_t jx, int32_t w, bool st_en, uint32_t np,
+                                              uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        int32_t *const pd = &rasp_lds[base + jx];
+        *(st_en ? pd : &rasp_lds[base + P]) = w;
+        d = *pd;
+        o = rasp_lds[base + np];
+        j = rasp_lds[base + nq];
     }
 };
 
@@ -232,7 +243,9 @@ __device__ __forceinline__ bool stuck(uint32_t op, int32_t j, int32_t a, int32_t
 // division and no special case.  Otherwise the common case -- operand word in
 // [0, n), i not within 4 of INT32_MAX, n >= 2 -- is straight-line code and
 // the general positions are computed out of line, behind one wave-uniform
-// branch that is not taken while no lane needs them.
+// branch that is not taken while no lane needs them (a split slot folds that
+// test into its one test for all uncommon work, and there a lane needs them
+// only when it uses its data position or jumps).
 // WM: words narrower than 32 bits (ws = 32 - w; POW2 then also needs n <= 2^w).
 // A tape staged in LDS is read one step ahead: the word at u0 is loaded with
 // the next instruction's words, so a READ costs no extra round trip.
@@ -265,8 +278,13 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         const bool fixed = !valid | (is_rd & !rd_ok) | (taken & (j == i));
         if (fixed | (left == 0u)) break;
 
+        const bool st_en = (op == 4u) | rd_ok;
+        const bool need = (op == 2u) | (op == 3u) | (op == 7u);
+        const bool app = (op == 7u) & (y0 < s);
+
         // positions: data word jj = j mod n, next instruction np, its operand nq
         uint32_t jj, seq, np, nq;
+        bool rare = false;
         const uint32_t i2 = static_cast<uint32_t>(i) + 2u;
         const int32_t ni = taken ? j : (WM ? sext(i2, ws) : static_cast<int32_t>(i2));
         if (POW2) {
@@ -281,39 +299,58 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             np = taken ? jj : seq;
             nq = np + 1u;
             nq = nq == n ? 0u : nq;
-            // with w < 32 a jump target j < n can also be the largest word,
-            // whose operand position i + 1 wraps
-            bool rare = (static_cast<uint32_t>(j) >= n) | (i >= imax - 3) | (n < 2u);
-            if (WM) rare |= j >= imax - 3;
-            // wave-uniform and out of line: when some lane needs the general
-            // positions every lane computes them and the rare lanes take them
-            if (__builtin_expect(__ballot(rare) != 0, 0)) {
-                const uint32_t jj2 = cmod(j, n);
-                const uint32_t seq2 = advance_pos(i, p, n, imax, WM ? ws : 0u);
-                const uint32_t np2 = taken ? jj2 : seq2;
-                const uint32_t nq2 = operand_pos(ni, np2, n, imax);
-                jj = rare ? jj2 : jj;
-                np = rare ? np2 : np;
-                nq = rare ? nq2 : nq;
+            // jj = j only for j in [0, n).  A split slot takes the general
+            // formulas only for lanes that use jj (a store, a data read, a
+            // jump); the others read the data word unconditionally.  With
+            // w < 32 a jump target j < n can also be the largest word, whose
+            // operand position i + 1 wraps.
+            bool j_out = static_cast<uint32_t>(j) >= n;
+            bool j_top = WM && (j >= imax - 3);
+            if (Mem::kColdIO) {
+                j_out &= st_en | need | taken;
+                j_top &= taken;
             }
+            rare = j_out | j_top | (i >= imax - 3) | (n < 2u);
         }
+        // the general positions, for the lanes that need them (every lane
+        // computes them: the caller branches on a wave-uniform test)
+        auto general_positions = [&]() {
+            const uint32_t jj2 = cmod(j, n);
+            const uint32_t seq2 = advance_pos(i, p, n, imax, WM ? ws : 0u);
+            const uint32_t np2 = taken ? jj2 : seq2;
+            const uint32_t nq2 = operand_pos(ni, np2, n, imax);
+            jj = rare ? jj2 : jj;
+            np = rare ? np2 : np;
+            nq = rare ? nq2 : nq;
+        };
 
-        const bool st_en = (op == 4u) | rd_ok;
         int32_t w = a;
-        if (Tape::kLds) {
-            w = rd_ok ? tv : a;                                // loaded one step ahead
-        } else if (Mem::kColdIO) {
-            if (__builtin_expect(__ballot(rd_ok) != 0, 0)) {
-                if (rd_ok) w = tape.ld(u0);
-            }
-        } else if (rd_ok) {
-            w = tape.ld(u0);
-        }
-        u0 += rd_ok ? 1u : 0u;
-        const bool need = (op == 2u) | (op == 3u) | (op == 7u);
         const int32_t jcur = j;
         int32_t d;
-        mem.step(jj, w, st_en, need, np, nq, d, o, j);
+        if constexpr (Mem::kColdIO) {
+            // one wave-uniform test for everything uncommon: general
+            // positions, a tape read, an output word, a word at or above P
+            const uint32_t jx = (st_en | need) ? jj : 0u;
+            bool cold = app | (max(max(jx, np), nq) >= mem.P);
+            if (!POW2) cold |= rare;
+            if (!Tape::kLds) cold |= rd_ok;
+            if (__builtin_expect(any_lane(cold), 0)) {
+                if (!POW2 && any_lane(rare)) general_positions();
+                if (Tape::kLds) w = rd_ok ? tv : a;
+                else if (rd_ok) w = tape.ld(u0);
+                mem.step(jj, w, st_en, need, np, nq, d, o, j);
+                out.st(y0, d, app);
+            } else {
+                if (Tape::kLds) w = rd_ok ? tv : a;
+                mem.step_near(jx, w, st_en, np, nq, d, o, j);
+            }
+        } else {
+            if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();
+            if (Tape::kLds) w = rd_ok ? tv : a;                // loaded one step ahead
+            else if (rd_ok) w = tape.ld(u0);
+            mem.step(jj, w, st_en, need, np, nq, d, o, j);
+        }
+        u0 += rd_ok ? 1u : 0u;
         if (Tape::kLds) tv = tape.ld(u0);
 
         const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);
@@ -322,12 +359,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         if (WM) na = static_cast<uint32_t>(sext(na, ws));
         na = op == 1u ? static_cast<uint32_t>(jcur) : na;
         a = static_cast<int32_t>(na);
-        const bool app = (op == 7u) & (y0 < s);
-        if (Mem::kColdIO) {
-            if (__builtin_expect(__ballot(app) != 0, 0)) out.st(y0, d, app);
-        } else {
-            out.st(y0, d, app);
-        }
+        if (!Mem::kColdIO) out.st(y0, d, app);
         y0 += app ? 1u : 0u;
         i = ni;
         p = np;

@@ -262,6 +262,16 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
     int32_t o = mem.ld(p);
     int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
     int32_t tv = Tape::kLds ? tape.ld(u0) : 0;          // u0 <= l: the region has l + 1 words
+    // split slot: a lane's step is uncommon when its largest position in use
+    // reaches min(n, P) (a word in HBM, or an operand outside [0, n) that
+    // needs the general positions) or when i is within 4 of the largest word
+    // (every step when n < 2)
+    uint32_t lim = 0u;
+    int32_t ilim = 0;
+    if constexpr (Mem::kColdIO) {
+        lim = POW2 ? mem.P : min(n, mem.P);
+        ilim = n < 2u ? INT32_MIN : imax - 3;
+    }
     uint32_t left = limit;
     for (;;) {
         const uint32_t op = static_cast<uint32_t>(o);
@@ -299,18 +309,13 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             np = taken ? jj : seq;
             nq = np + 1u;
             nq = nq == n ? 0u : nq;
-            // jj = j only for j in [0, n).  A split slot takes the general
-            // formulas only for lanes that use jj (a store, a data read, a
-            // jump); the others read the data word unconditionally.  With
-            // w < 32 a jump target j < n can also be the largest word, whose
-            // operand position i + 1 wraps.
-            bool j_out = static_cast<uint32_t>(j) >= n;
-            bool j_top = WM && (j >= imax - 3);
-            if (Mem::kColdIO) {
-                j_out &= st_en | need | taken;
-                j_top &= taken;
+            // jj = j only for j in [0, n); with w < 32 a jump target j < n can
+            // also be the largest word, whose operand position i + 1 wraps.
+            // (A split slot tests its lanes below, with its uncommon work.)
+            if constexpr (!Mem::kColdIO) {
+                rare = (static_cast<uint32_t>(j) >= n) | (i >= imax - 3) | (n < 2u);
+                if (WM) rare |= j >= imax - 3;
             }
-            rare = j_out | j_top | (i >= imax - 3) | (n < 2u);
         }
         // the general positions, for the lanes that need them (every lane
         // computes them: the caller branches on a wave-uniform test)
@@ -329,13 +334,21 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         int32_t d;
         if constexpr (Mem::kColdIO) {
             // one wave-uniform test for everything uncommon: general
-            // positions, a tape read, an output word, a word at or above P
+            // positions, a tape read, an output word, a word at or above P.
+            // jx is the data position of a lane that uses it, else 0; for
+            // n >= 2 the largest of jx, np and nq reaches n exactly when j is
+            // outside [0, n) and the lane uses jj or jumps to j.
             const uint32_t jx = (st_en | need) ? jj : 0u;
-            bool cold = app | (max(max(jx, np), nq) >= mem.P);
-            if (!POW2) cold |= rare;
+            const uint32_t m = max(max(jx, np), nq);
+            const bool j_top = WM && !POW2 && taken && (j >= imax - 3);
+            bool cold = app | (m >= lim) | j_top;
+            if (!POW2) cold |= i >= ilim;
             if (!Tape::kLds) cold |= rd_ok;
             if (__builtin_expect(any_lane(cold), 0)) {
-                if (!POW2 && any_lane(rare)) general_positions();
+                if (!POW2) {
+                    rare = (m >= n) | (i >= ilim) | j_top;
+                    if (any_lane(rare)) general_positions();
+                }
                 if (Tape::kLds) w = rd_ok ? tv : a;
                 else if (rd_ok) w = tape.ld(u0);
                 mem.step(jj, w, st_en, need, np, nq, d, o, j);

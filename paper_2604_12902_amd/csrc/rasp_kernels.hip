@@ -170,18 +170,20 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
         o = ld(np);
         j = ld(nq);
     }
-    // every access of every lane below P: straight LDS accesses.  jx is the
-    // data position of a lane that stores or reads its data word, else 0;
-    // the spare word after the P memory words takes the stores of lanes
-    // that do not store.
+    // every access of every lane below P, and the next operand at np + 1
+    // (no wrap): straight LDS accesses, the next instruction's two words in
+    // one read.  jx is the data position of a lane that stores or reads its
+    // data word, else 0; the spare word after the P memory words takes the
+    // stores of lanes that do not store.
     __device__ __forceinline__ void step_near(uint32_t jx, int32_t w, bool st_en, uint32_t np,
-                                              uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+                                              int32_t &d, int32_t &o, int32_t &j) const
     {
         int32_t *const pd = &rasp_lds[base + jx];
         *(st_en ? pd : &rasp_lds[base + P]) = w;
         d = *pd;
-        o = rasp_lds[base + np];
-        j = rasp_lds[base + nq];
+        const int32_t *const pn = &rasp_lds[base + np];
+        o = pn[0];
+        j = pn[1];
     }
 };
 
@@ -269,7 +271,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
     uint32_t lim = 0u;
     int32_t ilim = 0;
     if constexpr (Mem::kColdIO) {
-        lim = POW2 ? mem.P : min(n, mem.P);
+        lim = min(n, mem.P);
         ilim = n < 2u ? INT32_MIN : imax - 3;
     }
     uint32_t left = limit;
@@ -334,14 +336,16 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         int32_t d;
         if constexpr (Mem::kColdIO) {
             // one wave-uniform test for everything uncommon: general
-            // positions, a tape read, an output word, a word at or above P.
-            // jx is the data position of a lane that uses it, else 0; for
-            // n >= 2 the largest of jx, np and nq reaches n exactly when j is
-            // outside [0, n) and the lane uses jj or jumps to j.
+            // positions, a tape read, an output word, a word at or above P,
+            // an operand that wraps to word 0.  jx is the data position of a
+            // lane that uses it, else 0.  For n >= 2 the larger of jx and np
+            // reaches n exactly when j is outside [0, n) and the lane uses jj
+            // or jumps to j; np + 1 reaches min(n, P) when the next operand
+            // wraps (np = n - 1) or lies at or above P.
             const uint32_t jx = (st_en | need) ? jj : 0u;
-            const uint32_t m = max(max(jx, np), nq);
+            const uint32_t m = max(jx, np);
             const bool j_top = WM && !POW2 && taken && (j >= imax - 3);
-            bool cold = app | (m >= lim) | j_top;
+            bool cold = app | (max(m, np + 1u) >= lim) | j_top;
             if (!POW2) cold |= i >= ilim;
             if (!Tape::kLds) cold |= rd_ok;
             if (__builtin_expect(any_lane(cold), 0)) {
@@ -355,7 +359,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
                 out.st(y0, d, app);
             } else {
                 if (Tape::kLds) w = rd_ok ? tv : a;
-                mem.step_near(jx, w, st_en, np, nq, d, o, j);
+                mem.step_near(jx, w, st_en, np, d, o, j);
             }
         } else {
             if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();

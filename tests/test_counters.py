@@ -27,15 +27,33 @@ def test_lookup_needs_the_same_knobs_and_kernel_code(tmp_path):
 
 
 def test_committed_records_match_the_current_kernels():
-    """The plain-scale records under profiles/ were taken on the kernel code
-    in the tree (otherwise bench.py would report traffic as null)."""
+    """The records under profiles/ were taken on the kernel code in the tree
+    (otherwise bench.py would report traffic as null)."""
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    for k in ("persistent", "pack", "plain"):
-        with open(os.path.join(root, "profiles", "plain-scale_%s_traffic.json" % k)) as f:
-            rec = json.load(f)
-        assert rec["kernels_sha256"] == counters.kernels_sha256(), k
-        assert rec["runs"]
+    for w in ("plain-scale", "fig1", "uneven"):
+        for k in ("persistent", "pack", "plain"):
+            with open(os.path.join(root, "profiles", "%s_%s_traffic.json" % (w, k))) as f:
+                rec = json.load(f)
+            assert rec["kernels_sha256"] == counters.kernels_sha256(), (w, k)
+            assert rec["runs"]
+
+
+def test_headline_knobs_find_a_pack_record():
+    """Whatever epoch, slot or first-pass length the autotuner picks on
+    plain-scale, the bench line's dominant kernel (k_pack) has a record for
+    one, two and four batches in flight."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "profiles", "plain-scale_pack_traffic.json")
+    for epoch in (64, 256, 1024):
+        for lds in (128, 256):
+            for n in (1, 2, 4):
+                knobs = {"schedule": 2, "lds_words": lds, "first_pass": 64, "epoch": epoch,
+                         "waves_per_cu": 16, "first_pass_kind": 0, "c0_in_run": False}
+                if n > 1:
+                    knobs.update(batches_in_flight=n, cu_partition="split")
+                assert counters.lookup(path, knobs, "pack") is not None, knobs
 
 
 def test_pack_records_ignore_the_step_loop_knobs(tmp_path):

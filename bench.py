@@ -249,6 +249,10 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
 
 # batches in flight tried (five to eight were slower on plain-scale)
 INFLIGHT_CANDIDATES = (1, 2, 4)
+# knobs tried again once several batches are in flight: the ones whose best
+# value depends on how many lanes a batch has
+INFLIGHT_FIRST_PASSES = (16, 64, 256)
+INFLIGHT_EPOCHS = (64, 256, 1024)
 SERVE_PARTITIONS = 4
 
 
@@ -554,6 +558,33 @@ def main():
             if best is None or rate > best[1] / 0.97:
                 best = (cand, rate)
         n_flight = best[0]
+    if n_flight > 1:
+        # the autotuner picks the first-pass length and the epoch one batch
+        # at a time on the whole chip, where the first pass's survivors may
+        # all fit the resident lanes; on a 1/n share of the CUs the first pass
+        # takes n times as long and the survivors may not fit, so finished
+        # lanes wait for the next refill check.  Both are tried again with the
+        # batches in flight, one after the other (the current value stays
+        # unless another is at least 3% faster); a knob given on the command
+        # line is kept.
+        retune = []
+        if args.first_pass is None:
+            retune.append(("first pass", R.RASP_OPT_FIRST_PASS, INFLIGHT_FIRST_PASSES))
+        if args.epoch is None:
+            retune.append(("epoch", R.RASP_OPT_EPOCH, INFLIGHT_EPOCHS))
+        for name, opt, cands in retune:
+            cur = int(ctx.get(opt))
+            best = None
+            for v in (cur,) + tuple(x for x in cands if x != cur):
+                ctx.set(opt, v)
+                rate = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
+                                      total_steps, n_flight, steps=4 * n_flight, warmup=n_flight,
+                                      verify=False, quiet=True)["value"]
+                print("bench: trial %s %d with %d in flight: %.3e steps/s" % (name, v, n_flight, rate),
+                      flush=True)
+                if best is None or rate > best[1] / 0.97:
+                    best = (v, rate)
+            ctx.set(opt, best[0])
     if n_flight > 1:
         inflight = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
                                   total_steps, n_flight)

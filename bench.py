@@ -12,7 +12,8 @@ The value is the sum of retired transitions of a batch divided by the mean
 time per batch over the timed batches, with up to four batches in flight:
 one context per batch in flight, each with its own host thread and its own
 share of the compute units (rasp_create_on_cus), the count chosen from 1, 2
-and 4 by short untimed trials.  The same schedule one batch at a time
+and 4 by short untimed trials, after which the first-pass length and the
+epoch are tried again the same way in flight.  The same schedule one batch at a time
 (single_batch) and the plain one-machine-per-lane schedule are reported
 beside it.  Before reporting, the final state of every machine is checked
 against the CPU oracle (the oracle is run on the same batch on the host; its

@@ -264,10 +264,11 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
     int32_t o = mem.ld(p);
     int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
     int32_t tv = Tape::kLds ? tape.ld(u0) : 0;          // u0 <= l: the region has l + 1 words
-    // split slot: a lane's step is uncommon when its largest position in use
-    // reaches min(n, P) (a word in HBM, or an operand outside [0, n) that
-    // needs the general positions) or when i is within 4 of the largest word
-    // (every step when n < 2)
+    // split slot: a lane's step is uncommon when its largest position in use,
+    // np + 1 included, reaches min(n, P) (a word in HBM, a next operand that
+    // wraps to word 0, or an operand outside [0, n) that needs the general
+    // positions) or when i is within 4 of the largest word (every step when
+    // n < 2)
     uint32_t lim = 0u;
     int32_t ilim = 0;
     if constexpr (Mem::kColdIO) {

@@ -1,6 +1,7 @@
 """The traffic records bench.py reports: keyed by the scheduling knobs and
 by the kernel source's code (comments and whitespace aside)."""
 import json
+import os
 
 from paper_2604_12902_amd import counters
 
@@ -70,3 +71,40 @@ def test_pack_records_ignore_the_step_loop_knobs(tmp_path):
     assert counters.lookup(str(path), dict(rec, epoch=64), "persistent") is None
     assert counters.lookup(str(path), dict(rec, epoch=64), "plain") == 7.0
     assert counters.lookup(str(path), dict(rec, first_pass=16), "plain") is None
+
+
+def _counter_db(d, counter, rows):
+    """A rocprofv3-shaped result: one counters_collection row per (kernel,
+    dispatch, counter instance), values in KiB."""
+    import sqlite3
+    os.makedirs(d, exist_ok=True)
+    con = sqlite3.connect(os.path.join(d, "pmc_results.db"))
+    con.execute("create table counters_collection (kernel_name text, dispatch_id integer, "
+                "counter_name text, value real, duration integer)")
+    for name, disp, val in rows:
+        con.execute("insert into counters_collection values (?, ?, ?, ?, 0)", (name, disp, counter, val))
+    con.commit()
+    con.close()
+
+
+def test_measure_scales_by_the_copy_and_averages_dispatches(tmp_path):
+    """A 1 GiB copy that reads 512 Ki KiB of FETCH_SIZE scales fetch by 2; a
+    kernel's counter instances are summed per dispatch and averaged over
+    dispatches (or over the last N)."""
+    gib = 1 << 30
+    f, w = str(tmp_path / "f"), str(tmp_path / "w")
+    copy = "__amd_rocclr_copyBuffer"
+    _counter_db(f, "FETCH_SIZE", [(copy, 1, 262144.0), (copy, 1, 262144.0),
+                                  ("k_pack(x)", 2, 100.0), ("k_pack(x)", 2, 50.0),
+                                  ("k_pack(x)", 3, 300.0), ("k_plain(x)", 4, 7.0)])
+    _counter_db(w, "WRITE_SIZE", [(copy, 1, 1048576.0), ("k_pack(x)", 2, 10.0),
+                                  ("k_pack(x)", 3, 30.0)])
+    res = counters.measure(f, w, gib, "k_pack")
+    assert res["fetch_scale"] == 2.0 and res["write_scale"] == 1.0
+    assert res["fetch_kernel_dispatches"] == 2
+    assert res["fetch_bytes_per_launch"] == (150.0 + 300.0) / 2 * 1024 * 2
+    assert res["write_bytes_per_launch"] == (10.0 + 30.0) / 2 * 1024
+    assert res["bytes_per_launch"] == res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"]
+    last = counters.measure(f, w, gib, "k_pack", last=1)
+    assert last["fetch_bytes_per_launch"] == 300.0 * 1024 * 2
+    assert last["write_bytes_per_launch"] == 30.0 * 1024

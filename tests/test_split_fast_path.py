@@ -54,3 +54,24 @@ def test_wrap_and_slot_end_are_not_fast():
             assert max(0, n - 1, n) >= lim          # np = n - 1: np + 1 = n
             if n > P:
                 assert max(0, P - 1, P) >= lim      # np = P - 1: np + 1 = P
+
+
+def test_common_positions_of_the_other_loops_are_exact():
+    """Memory in HBM or whole in LDS: a lane is rare when j is outside [0, n),
+    i is within 4 of the largest word, or n < 2; otherwise jj = j, the next
+    instruction and its operand (wrapping to word 0) are the Euclidean ones."""
+    js = np.arange(-70, 90, dtype=np.int64)
+    for n in range(2, 41):
+        for p in range(n):
+            i = p + 5 * n
+            for taken in (False, True):
+                ju = js & 0xFFFFFFFF
+                rare = ju >= n
+                seq = p + 2 - n if p + 2 >= n else p + 2
+                np_ = np.where(taken, ju, seq)
+                nq = np.where(np_ + 1 == n, 0, np_ + 1)
+                j = js[~rare]
+                assert (ju[~rare] == _emod(j, n)).all()
+                want_np = _emod(j, n) if taken else np.full(j.shape, _emod(i + 2, n))
+                assert (np_[~rare] == want_np).all()
+                assert (nq[~rare] == _emod(want_np + 1, n)).all()

@@ -20,10 +20,12 @@ against the CPU oracle (the oracle is run on the same batch on the host; its
 timing is the cpu_baseline).
 
 Workloads (sizes of the stated populations):
+  uneven       4,194,304 programs of 8..512 instructions (lengths log-uniform),
+               n = 64..1,024 words, budget 65,536 (default: the largest
+               population that fits one GPU)
   plain-scale  1,048,576 random programs x 64 instructions, n = 256,
-               tape 32 words, output capacity 16, budget 4,096 (default)
+               tape 32 words, output capacity 16, budget 4,096
   plain-small  4,096 x 16 instructions, n = 32, budget 256
-  uneven       4,194,304 programs of 8..512 instructions, budget 65,536
   rollouts     262,144 counted-loop array programs, n = 2,048, budget 2^20
   fig1         262,144 uniform Sec. 2.2 programs of 100 terminals, word RASP,
                n = 250, l = 10, s = 2, budget 10^6 (the Sec. 3 evaluation)
@@ -50,7 +52,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain-scale",
+    ap.add_argument("--workload", default="uneven",
                     choices=["plain-scale", "plain-small", "uneven", "rollouts", "fig1", "serve"])
     ap.add_argument("--requests", type=int, default=500, help="serve: requests per run")
     ap.add_argument("--loads", default="0.5,0.8,1.0", help="serve: offered load, fractions of capacity")
@@ -83,6 +85,11 @@ def parse():
                     help="build c0 inside the run (RASP_DESC_LAZY) instead of in rasp_load_batch")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default knobs instead of running rasp_autotune")
+    ap.add_argument("--retune", action="store_true",
+                    help="search the knobs again even when the autotune cache holds them for this "
+                         "device, batch and library code")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file (default: the package's tune_cache.json)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="bytes of one plain device-to-device copy run before the workload "
                          "(the reference dispatch for HBM byte counters)")
@@ -120,15 +127,26 @@ def cpu_model() -> str:
     return "%s (%d logical CPUs)" % (name, os.cpu_count() or 0)
 
 
+def oracle_compiler() -> str:
+    """Version of the C compiler that builds the oracle."""
+    import subprocess
+    try:
+        out = subprocess.run(["gcc", "--version"], capture_output=True, text=True, timeout=10).stdout
+        return out.splitlines()[0].strip() + " -O3"
+    except (OSError, subprocess.SubprocessError, IndexError):
+        return "unknown"
+
+
 def bytes_per_step(mix: np.ndarray) -> float:
     """Algorithmic bytes per retired step for a retired-opcode mix:
-    8 B fetch (opcode + operand) always; +4 B data read for ADD/SUB/MUL and
-    PRINT; +4 B data write for STORE; READ +4 B tape read +4 B memory write;
-    an appended PRINT +4 B output write."""
+    8 B fetch (opcode + operand) always; +4 B data read for ADD/SUB/MUL;
+    +4 B data write for STORE; READ +4 B tape read +4 B memory write; a
+    PRINT that appends +4 B data read +4 B output write (a PRINT past the
+    output capacity moves no word)."""
     steps = float(mix[1:9].sum())
     if steps == 0:
         return 0.0
-    extra = 4.0 * (mix[2] + mix[3] + mix[7]) + 4.0 * mix[4] + 8.0 * mix[6] + 4.0 * mix[9]
+    extra = 4.0 * (mix[2] + mix[3]) + 4.0 * mix[4] + 8.0 * mix[6] + 8.0 * mix[9]
     return 8.0 + float(extra) / steps
 
 
@@ -263,7 +281,7 @@ def arena_inflight(fp):
 
 
 def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_steps, n, steps=None,
-                   warmup=None, verify=True, quiet=False):
+                   warmup=None, verify=True, quiet=False, ref_digest=None):
     """The persistent schedule with `n` batches in flight: one
     context per batch in flight, each with its own stream and its own host
     thread that loads, runs and fetches its share of the batches one after
@@ -301,6 +319,10 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                     y0=torch.empty(N, dtype=torch.int32, device=dev),
                     y=torch.empty(ny, dtype=torch.int32, device=dev))
     outs = [new_outs() for _ in range(n)]
+    if ref_digest is not None:
+        # every machine's final memory, compared as its FNV-1a-64 digest
+        for o in outs:
+            o["mem_digest"] = torch.empty(N, dtype=torch.int64, device=dev)
 
     def drive(c, count, lat, errors):
         # one host thread per context: load, run, fetch, free, one batch after
@@ -354,6 +376,9 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                     raise SystemExit("bench: NOT bit-exact with %d batches in flight: %s" % (n, k))
             if not np.array_equal(outs[c]["y"].cpu().numpy(), ref.Y):
                 raise SystemExit("bench: NOT bit-exact with %d batches in flight: output words" % n)
+            if ref_digest is not None and not np.array_equal(
+                    outs[c]["mem_digest"].cpu().numpy().view(np.uint64), ref_digest):
+                raise SystemExit("bench: NOT bit-exact with %d batches in flight: memory digests" % n)
     for c in ctxs:
         if c is not ctx:
             c.close()
@@ -399,8 +424,9 @@ def main():
     # ---- CPU oracle: the reference result and the CPU baseline ----
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     cores = max(1, min(cores, 64))
-    t0 = time.time()
+    # c0 is built outside the timer: the baseline times the step loop only
     ref = oracle.init(batch)
+    t0 = time.time()
     mix = oracle.advance_mix(ref, budget, threads=cores)
     cpu_s = time.time() - t0
     total_steps = int(ref.steps.sum())
@@ -411,8 +437,8 @@ def main():
     if not args.no_cpu_baseline:
         # one host thread on every cores-th machine: about the CPU work of the run above
         sub = batch.subset(np.arange(0, batch.N, cores))
-        t1 = time.time()
         st1 = oracle.init(sub)
+        t1 = time.time()
         oracle.advance(st1, budget, threads=1)
         one_s = time.time() - t1
         one = {"value": float(st1.steps.sum()) / one_s,
@@ -450,8 +476,19 @@ def main():
     ctx = R.Context(arena)
     torch.cuda.synchronize()
 
+    # knobs: from the autotune cache when it holds this device, batch and
+    # library code, else searched (untimed) and stored there
+    from paper_2604_12902_amd import tune_cache
+    props = torch.cuda.get_device_properties(0)
+    cache_key = tune_cache.make_key(getattr(props, "gcnArchName", "unknown"), props.multi_processor_count,
+                                    batch, budget, extra="lazy=%d cus=%s" % (args.lazy, args.inflight_cus))
+    cache_path = args.tune_cache or tune_cache.PATH
+    cached = None if (args.retune or args.no_autotune) else tune_cache.get(cache_key, cache_path)
     tuned = None
-    if not args.no_autotune:
+    if cached is not None:
+        tuned = cached["autotune"]
+        print("bench: knobs from the autotune cache: %s" % cached, flush=True)
+    elif not args.no_autotune:
         # the library's autotuner picks the knobs on a snapshot (untimed)
         h = R.rasp_load_batch(ctx.handle, desc)
         tuned = R.rasp_autotune(ctx.handle, h, budget, max_vms=tune_vms)
@@ -543,6 +580,13 @@ def main():
     inflight = None
     n_flight = args.inflight
     configure(R.RASP_SCHED_PERSISTENT)                  # the knobs the contexts copy
+    from_cache = cached is not None and n_flight == 0
+    if from_cache:
+        n_flight = int(cached["inflight"])
+        if args.first_pass is None:
+            ctx.set(R.RASP_OPT_FIRST_PASS, int(cached["inflight_first_pass"]))
+        if args.epoch is None:
+            ctx.set(R.RASP_OPT_EPOCH, int(cached["inflight_epoch"]))
     if n_flight == 0:
         # batches in flight chosen like the other knobs: a short untimed trial
         # of each candidate (2n batches after n warm-up ones); a larger count
@@ -559,7 +603,7 @@ def main():
             if best is None or rate > best[1] / 0.97:
                 best = (cand, rate)
         n_flight = best[0]
-    if n_flight > 1:
+    if n_flight > 1 and not from_cache:
         # the autotuner picks the first-pass length and the epoch one batch
         # at a time on the whole chip, where the first pass's survivors may
         # all fit the resident lanes; on a 1/n share of the CUs the first pass
@@ -586,9 +630,14 @@ def main():
                 if best is None or rate > best[1] / 0.97:
                     best = (v, rate)
             ctx.set(opt, best[0])
+    if tuned is not None and cached is None and args.inflight == 0:
+        tune_cache.put(cache_key, {"autotune": tuned, "inflight": n_flight,
+                                   "inflight_first_pass": int(ctx.get(R.RASP_OPT_FIRST_PASS)),
+                                   "inflight_epoch": int(ctx.get(R.RASP_OPT_EPOCH))}, cache_path)
     if n_flight > 1:
         inflight = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
-                                  total_steps, n_flight)
+                                  total_steps, n_flight,
+                                  ref_digest=oracle.digest(ref) if args.verify == "full" else None)
 
     # the headline: the persistent schedule with the batches in flight the
     # run was asked for (one: results["persistent"])
@@ -639,8 +688,9 @@ def main():
         cpu = {"value": total_steps / cpu_s, "unit": "VM instructions retired/s", "cores": cores,
                "kind": "oracle",
                "sample": "the whole batch (%d machines, %d retired steps), %d host threads, "
-                         "static round-robin striping" % (N, total_steps, cores),
-               "one_thread": one, "cpu_model": cpu_model()}
+                         "static round-robin striping; the step loop timed (c0 built before the "
+                         "timer), with the retired-opcode histogram counted" % (N, total_steps, cores),
+               "one_thread": one, "cpu_model": cpu_model(), "compiler": oracle_compiler()}
 
     line = {
         "metric": "VM instructions retired/sec (1 GPU), bit-exact; persistent vs plain; p50/p99",
@@ -651,7 +701,7 @@ def main():
         "config": {"workload": batch.name, "num_vms": N, "budget": budget,
                    "retired_steps_per_batch": total_steps, "schedule": "persistent",
                    "first_pass": fp_pass, "lds_words": head["knobs"]["lds_words"],
-                   "c0_in_run": args.lazy, "autotuned": tuned is not None,
+                   "c0_in_run": args.lazy, "autotuned": tuned is not None, "knobs_from_cache": cached is not None,
                    "epoch": head["knobs"]["epoch"], "waves_per_cu": head["knobs"]["waves_per_cu"],
                    "first_pass_kind": head["knobs"]["first_pass_kind"],
                    "batches_in_flight": n_flight if inflight is not None else 1,

@@ -26,7 +26,8 @@ Workloads (sizes of the stated populations):
   plain-scale  1,048,576 random programs x 64 instructions, n = 256,
                tape 32 words, output capacity 16, budget 4,096
   plain-small  4,096 x 16 instructions, n = 32, budget 256
-  rollouts     262,144 counted-loop array programs, n = 2,048, budget 2^20
+  rollouts     262,144 counted-loop array programs (each machine its own), n = 2,048,
+               budget 2^20
   fig1         262,144 uniform Sec. 2.2 programs of 100 terminals, word RASP,
                n = 250, l = 10, s = 2, budget 10^6 (the Sec. 3 evaluation)
 """
@@ -63,8 +64,8 @@ def parse():
                          "or four, whichever serves the closed loop faster)")
     ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
     ap.add_argument("--gen-workers", type=int, default=0,
-                    help="processes generating the fig1 programs (0: up to 16; 1 under a "
-                         "profiler, which would otherwise follow every child process)")
+                    help="processes generating the fig1 and rollout programs (0: up to 16; 1 under "
+                         "a profiler, which would otherwise follow every child process)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-schedule comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verify", choices=["full", "sample", "none"], default="full")
@@ -110,7 +111,7 @@ def make_batch(args):
         return W.config3(**kw)
     if args.workload == "fig1":
         return W.fig1(workers=args.gen_workers or min(16, os.cpu_count() or 1), **kw)
-    return W.config4(**kw)
+    return W.config4(workers=args.gen_workers or min(16, os.cpu_count() or 1), **kw)
 
 
 def cpu_model() -> str:

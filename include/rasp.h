@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define RASP_ABI_VERSION 2u
+#define RASP_ABI_VERSION 3u
 
 typedef struct rasp_ctx rasp_ctx;
 typedef uint64_t rasp_batch;                 /* 0 is never a valid handle */
@@ -238,11 +238,20 @@ int rasp_run(rasp_ctx *ctx, rasp_batch b, uint64_t budget);
  */
 int rasp_run_multi(rasp_ctx *ctx, const rasp_batch *bs, const uint64_t *budgets, uint32_t k);
 
-/* rasp_poll: *done = 1 when all work queued so far on ctx has finished. */
-int rasp_poll(rasp_ctx *ctx, int *done);
+/*
+ * rasp_poll: *done = 1 when the work queued so far for batch b (its load and
+ * runs) has finished, else 0; never waits.  b = 0 asks about all work queued
+ * on the context.
+ * Errors: INVAL (done NULL), STATE (bad handle), DEVICE.
+ */
+int rasp_poll(rasp_ctx *ctx, rasp_batch b, int *done);
 
-/* rasp_sync: wait for all work queued on ctx. */
-int rasp_sync(rasp_ctx *ctx);
+/*
+ * rasp_sync: wait until the work queued so far for batch b has finished
+ * (b = 0: all work queued on the context).
+ * Errors: STATE (bad handle), DEVICE.
+ */
+int rasp_sync(rasp_ctx *ctx, rasp_batch b);
 
 /*
  * rasp_fetch_outputs: wait for the batch's queued work, then copy the requested

@@ -86,6 +86,8 @@ struct Batch {
     bool all_pow2 = false;               // every n a power of two
     bool uniform_dense = false;          // every n a multiple of 4: padded == dense
     bool status_stale = true;            // status not yet computed since the load
+    hipEvent_t done = nullptr;           // recorded after the batch's latest queued work
+    ~Batch() { if (done) (void)hipEventDestroy(done); }
 };
 
 uint64_t meta_bytes(uint64_t N)
@@ -599,6 +601,15 @@ int table_slot(rasp_ctx *c, BatchTable **host, BatchTable **devp, int *slot)
     return RASP_OK;
 }
 
+// record the batch's event after the work queued for it so far (the event is
+// created with the batch's first queued work)
+int mark_queued(rasp_ctx *c, Batch *b)
+{
+    if (!b->done) HIPCHK(c, hipEventCreateWithFlags(&b->done, hipEventDisableTiming));
+    HIPCHK(c, hipEventRecord(b->done, c->stream));
+    return RASP_OK;
+}
+
 int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
 {
     const uint32_t isa = bs[0]->dev.isa;
@@ -796,8 +807,9 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     *out = nullptr;
     if (arena_bytes < (1ull << 20)) return fail(nullptr, RASP_E_INVAL, "arena must be at least 1 MiB");
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
-        return fail(nullptr, RASP_E_INVAL, "no HIP device %d", device);
+    const hipError_t ec = hipGetDeviceCount(&ndev);
+    if (ec != hipSuccess) return fail(nullptr, RASP_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(ec));
+    if (device < 0 || device >= ndev) return fail(nullptr, RASP_E_INVAL, "no HIP device %d", device);
     auto c = std::unique_ptr<rasp_ctx>(new (std::nothrow) rasp_ctx());
     if (!c) return fail(nullptr, RASP_E_NOMEM, "host allocation failed");
     c->device = device;
@@ -855,8 +867,9 @@ int rasp_create_on_cus(rasp_ctx **out, int device, void *arena, uint64_t arena_b
     if (!out) return fail(nullptr, RASP_E_INVAL, "out is NULL");
     *out = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
-        return fail(nullptr, RASP_E_INVAL, "no HIP device %d", device);
+    const hipError_t ec = hipGetDeviceCount(&ndev);
+    if (ec != hipSuccess) return fail(nullptr, RASP_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(ec));
+    if (device < 0 || device >= ndev) return fail(nullptr, RASP_E_INVAL, "no HIP device %d", device);
     hipDeviceProp_t prop;
     hipError_t e = hipSetDevice(device);
     if (!e) e = hipGetDeviceProperties(&prop, device);
@@ -943,6 +956,7 @@ int rasp_load_batch(rasp_ctx *c, const rasp_batch_desc *d, rasp_batch *out)
     std::unique_ptr<Batch> B;
     if ((rc = load_common(c, d, B))) return rc;
     const rasp_batch h = c->next_handle++;
+    if ((rc = mark_queued(c, B.get()))) return rc;
     c->batches[h] = std::move(B);
     *out = h;
     return RASP_OK;
@@ -1007,6 +1021,7 @@ int rasp_load_state(rasp_ctx *c, const rasp_batch_desc *d, const rasp_outputs *s
     if (*errw) { fail(c, RASP_E_INVAL, "a word of the state is not a %u-bit value", b.wbits); return undo(RASP_E_INVAL); }
     arena_free(c, &tmp);
     const rasp_batch h = c->next_handle++;
+    if ((rc = mark_queued(c, B.get()))) return rc;
     c->batches[h] = std::move(B);
     *out = h;
     return RASP_OK;
@@ -1045,25 +1060,40 @@ int rasp_run_multi(rasp_ctx *c, const rasp_batch *hs, const uint64_t *budgets, u
         if (!any) break;
         if ((rc = run_batches(c, bs.data(), b32.data(), k))) return rc;
     }
+    for (uint32_t t = 0; t < k; ++t)
+        if ((rc = mark_queued(c, bs[t]))) return rc;
     return RASP_OK;
 }
 
-int rasp_poll(rasp_ctx *c, int *done)
+int rasp_poll(rasp_ctx *c, rasp_batch h, int *done)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (!done) return fail(c, RASP_E_INVAL, "done is NULL");
-    const hipError_t e = hipStreamQuery(c->stream);
+    hipError_t e;
+    if (h == 0) {
+        e = hipStreamQuery(c->stream);
+    } else {
+        Batch *b = find(c, h);
+        if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
+        e = b->done ? hipEventQuery(b->done) : hipSuccess;
+    }
     if (e == hipSuccess) { *done = 1; return RASP_OK; }
     if (e == hipErrorNotReady) { *done = 0; return RASP_OK; }
-    return fail(c, RASP_E_DEVICE, "stream query: %s", hipGetErrorString(e));
+    return fail(c, RASP_E_DEVICE, "completion query: %s", hipGetErrorString(e));
 }
 
-int rasp_sync(rasp_ctx *c)
+int rasp_sync(rasp_ctx *c, rasp_batch h)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h == 0) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return RASP_OK;
+    }
+    Batch *b = find(c, h);
+    if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
+    if (b->done) HIPCHK(c, hipEventSynchronize(b->done));
     return RASP_OK;
 }
 

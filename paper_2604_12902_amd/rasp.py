@@ -16,11 +16,15 @@ import os
 from dataclasses import dataclass
 
 import numpy as np
+# torch first: it loads the HIP runtime it was built with, and librasp's
+# libamdhip64.so.7 then resolves to that same copy, so that device memory and
+# streams from torch and the library's calls share one runtime
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librasp.so")
 
-RASP_ABI_VERSION = 2
+RASP_ABI_VERSION = 3
 RASP_OK, RASP_E_INVAL, RASP_E_NOMEM, RASP_E_DEVICE, RASP_E_STATE, RASP_E_BUSY = 0, -1, -2, -3, -4, -5
 RASP_ISA_WORD, RASP_ISA_CLASSIC = 0, 1
 RASP_RUNNING, RASP_HALTED = 0, 1
@@ -84,8 +88,8 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(u64)], i32),
         "rasp_run": ([P, u64, u64], i32),
         "rasp_run_multi": ([P, P, P, u32], i32),
-        "rasp_poll": ([P, ctypes.POINTER(i32)], i32),
-        "rasp_sync": ([P], i32),
+        "rasp_poll": ([P, u64, ctypes.POINTER(i32)], i32),
+        "rasp_sync": ([P, u64], i32),
         "rasp_fetch_outputs": ([P, u64, ctypes.POINTER(rasp_outputs)], i32),
         "rasp_batch_info": ([P, u64, P, P, P, P], i32),
         "rasp_free_batch": ([P, u64], i32),
@@ -228,14 +232,14 @@ def rasp_run_multi(ctx, batches, budgets) -> None:
     _check(_lib.rasp_run_multi(ctx, _ptr(hs), _ptr(bs), len(hs)), ctx)
 
 
-def rasp_poll(ctx) -> bool:
+def rasp_poll(ctx, batch: int = 0) -> bool:
     done = ctypes.c_int()
-    _check(_lib.rasp_poll(ctx, ctypes.byref(done)), ctx)
+    _check(_lib.rasp_poll(ctx, batch, ctypes.byref(done)), ctx)
     return bool(done.value)
 
 
-def rasp_sync(ctx) -> None:
-    _check(_lib.rasp_sync(ctx), ctx)
+def rasp_sync(ctx, batch: int = 0) -> None:
+    _check(_lib.rasp_sync(ctx, batch), ctx)
 
 
 def rasp_batch_info(ctx, batch: int, steps_sum: bool = False) -> dict:
@@ -385,8 +389,11 @@ class Context:
         rasp_free_batch(self.handle, b)
         self._keep.pop(b, None)
 
-    def sync(self) -> None:
-        rasp_sync(self.handle)
+    def sync(self, b: int = 0) -> None:
+        rasp_sync(self.handle, b)
+
+    def poll(self, b: int = 0) -> bool:
+        return rasp_poll(self.handle, b)
 
     def info(self, b: int, steps_sum: bool = False) -> dict:
         return rasp_batch_info(self.handle, b, steps_sum)

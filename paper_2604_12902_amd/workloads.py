@@ -320,32 +320,48 @@ def rollout_program(seed: int, index: int):
             return ast
 
 
-def config4(seed: int = 3, num_vms: int = 1 << 18, num_distinct: int = 2048,
-            budget: int = ROLLOUT_BUDGET) -> Batch:
-    """Array-program rollouts: counted-loop programs over an input array of 1,024
-    words uniform on [-2^15, 2^15), lowered to the classic RASP (about 128 to
-    384 instructions each), memory 2,048 words, output capacity 1,024, budget
-    2^20.  `num_distinct` program structures are generated (program v has
-    structure v mod num_distinct); every machine has its own input array.
-    Draw order: structures by (seed, index) streams; tapes (N x 1024) from
-    PCG64(seed)."""
+def _rollout_chunk(job):
+    seed, start, stop = job
     progs = []
-    for d in range(min(num_distinct, num_vms)):
+    for d in range(start, stop):
         pairs, data_words = dsl.lower_classic(rollout_program(seed, d))
         if 2 * len(pairs) + data_words > ROLLOUT_MEM:
             raise RuntimeError("rollout program does not fit its memory")
         progs.append(np.array(dsl.flatten(pairs), dtype=np.int32))
+    return progs
+
+
+def config4(seed: int = 3, num_vms: int = 1 << 18, num_distinct: int | None = None,
+            budget: int = ROLLOUT_BUDGET, workers: int = 1) -> Batch:
+    """Array-program rollouts: counted-loop programs over an input array of 1,024
+    words uniform on [-2^15, 2^15), lowered to the classic RASP (about 128 to
+    384 instructions each), memory 2,048 words, output capacity 1,024, budget
+    2^20.  `num_distinct` program structures are generated (program v has
+    structure v mod num_distinct; default: every machine its own program);
+    every machine has its own input array.  Draw order: structures by
+    (seed, index) streams; tapes (N x 1024) from PCG64(seed).  Structures are
+    lowered in chunks of 4,096 (in `workers` spawned processes when it is
+    above 1; the result does not depend on it)."""
+    distinct = num_vms if num_distinct is None else min(num_distinct, num_vms)
+    chunk = 4096
+    jobs = [(seed, a, min(distinct, a + chunk)) for a in range(0, distinct, chunk)]
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            parts = pool.map(_rollout_chunk, jobs)
+    else:
+        parts = [_rollout_chunk(j) for j in jobs]
+    progs = [p for part in parts for p in part]
     which = np.arange(num_vms) % len(progs)
     plen = np.array([len(progs[w]) for w in which], dtype=np.int64)
-    prog = np.concatenate([progs[w] for w in which]) if num_vms <= len(progs) else \
-        np.concatenate(progs * (num_vms // len(progs)) + progs[:num_vms % len(progs)])
+    prog = np.concatenate([progs[w] for w in which])
     rng = np.random.Generator(np.random.PCG64(seed))
     tape = rng.integers(-(1 << 15), 1 << 15, size=(num_vms, ROLLOUT_ARRAY), dtype=np.int32)
     return Batch(ISA_CLASSIC, prog, _offsets(plen), np.full(num_vms, ROLLOUT_MEM, np.uint32),
                  tape.reshape(-1), np.arange(num_vms + 1, dtype=np.uint64) * np.uint64(ROLLOUT_ARRAY),
                  np.full(num_vms, ROLLOUT_ARRAY, np.uint32),
                  np.full(num_vms, ROLLOUT_OUT, np.uint32), budget=budget,
-                 name="rollouts 256Kx[128,384] n=2048 budget=2^20",
+                 name="rollouts %dx[128,384] n=2048 budget=2^20" % num_vms,
                  meta=dict(seed=seed, num_distinct=len(progs)))
 
 

@@ -149,6 +149,49 @@ def test_uneven_batch_reduced_bit_exact(ctx, rasp, sched):
     compare(run_gpu(ctx, b, b.budget), oracle.run(b, b.budget, threads=8))
 
 
+@pytest.fixture(scope="module")
+def rollouts_reduced():
+    b = W.config4(num_vms=512)
+    return b, oracle.run(b, b.budget, threads=8)
+
+
+@pytest.mark.parametrize("sched", list(SCHEDULES))
+def test_rollouts_reduced_bit_exact(ctx, rasp, rollouts_reduced, sched):
+    """512 distinct counted-loop array programs (n = 2,048, budget 2^20) under
+    every schedule: memory slices larger than any slot, long READ and PRINT
+    bursts."""
+    b, want = rollouts_reduced
+    print("case: rollouts N=%d sched=%s" % (b.N, sched), flush=True)
+    configure(ctx, rasp, sched)
+    compare(run_gpu(ctx, b, b.budget), want)
+
+
+def test_poll_and_sync_per_batch(ctx, rasp):
+    """rasp_poll / rasp_sync on one batch wait for that batch's queued work;
+    batch 0 means all work of the context; an unknown handle is an error."""
+    configure(ctx, rasp, "firstpass-lds64")
+    b = W.config1()
+    h1, h2 = ctx.load(b), ctx.load(b)
+    ctx.run(h1, 256)
+    ctx.run(h2, 100)
+    ctx.sync(h1)
+    assert ctx.poll(h1)
+    ctx.sync(h2)
+    assert ctx.poll(h2) and ctx.poll(0)
+    ctx.run(h2, 156)
+    ctx.sync(0)
+    assert ctx.poll(h2)
+    want = oracle.run(b, 256)
+    compare(ctx.fetch(h1, mem=True), want)
+    compare(ctx.fetch(h2, mem=True), want)
+    ctx.free(h1)
+    with pytest.raises(rasp.RaspError, match="unknown batch handle"):
+        ctx.poll(h1)
+    with pytest.raises(rasp.RaspError, match="unknown batch handle"):
+        ctx.sync(h1)
+    ctx.free(h2)
+
+
 def test_split_budget_and_halted_machines(ctx, rasp):
     configure(ctx, rasp, "firstpass-lds64")
     b = W.config1()

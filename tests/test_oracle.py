@@ -156,13 +156,25 @@ def test_rollout_programs_match_direct_evaluation_and_never_overflow():
         tape = b.tape[int(b.tape_off[v]):int(b.tape_off[v + 1])].tolist()
         want = dsl_eval.eval_counted(W.rollout_program(3, v), tape, int(b.out_cap[v]))
         assert st.out_of(v)[:int(st.y0[v])].tolist() == want
-    for v in range(2):
+
+
+@pytest.mark.parametrize("part", range(4))
+def test_rollout_population_never_leaves_int32(part):
+    """The first 256 machines of the full rollout population (machine v of a
+    smaller batch is machine v of the full one: programs come from (seed, v)
+    streams and tapes row by row), run over unbounded integers: no value ever
+    leaves int32, and the Z machine retires the same steps and prints the same
+    words as the int32 oracle."""
+    b = W.config4(num_vms=256)
+    lo, hi = 64 * part, 64 * (part + 1)
+    st = oracle.run(b.subset(np.arange(lo, hi)), b.budget)
+    for v in range(lo, hi):
         prog = b.prog[int(b.prog_off[v]):int(b.prog_off[v + 1])].tolist()
         tape = b.tape[int(b.tape_off[v]):int(b.tape_off[v + 1])].tolist()
         z = zinterp.zrun(b.isa, prog, tape, W.ROLLOUT_MEM, W.ROLLOUT_ARRAY, W.ROLLOUT_OUT,
                          b.budget)
-        assert not z["overflow"]
-        assert z["steps"] == int(st.steps[v]) and z["Y"] == st.out_of(v).tolist()
+        assert not z["overflow"], v
+        assert z["steps"] == int(st.steps[v - lo]) and z["Y"] == st.out_of(v - lo).tolist(), v
 
 
 # ---- invariants on a random batch (the plain small workload) ------------------------

@@ -239,6 +239,23 @@ int rasp_run(rasp_ctx *ctx, rasp_batch b, uint64_t budget);
 int rasp_run_multi(rasp_ctx *ctx, const rasp_batch *bs, const uint64_t *budgets, uint32_t k);
 
 /*
+ * rasp_run_noalloc: rasp_run for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation).  The same kernels and results as rasp_run, but the queue
+ * counters, batch tables and first-pass survivor list live in one fixed
+ * device array of the library (16 MiB per GPU, held until the process ends)
+ * instead of the context arena; the call allocates nothing, creates no
+ * events (kernel timing is off for it) and never captures a graph.  The
+ * batch (inputs and outputs) is the caller's, loaded as usual.  Every call on
+ * one GPU shares that array: calls that overlap on one GPU, from any context
+ * or thread, race and must be serialised by the caller.  The queue counters
+ * are cleared by a fill kernel at the start of every launch.
+ * Limit: at most 4,194,304 machines in the batch.
+ * Errors: INVAL (batch above the limit), STATE (bad handle), DEVICE.
+ */
+int rasp_run_noalloc(rasp_ctx *ctx, rasp_batch b, uint64_t budget);
+
+/*
  * rasp_poll: *done = 1 when the work queued so far for batch b (its load and
  * runs) has finished, else 0; never waits.  b = 0 asks about all work queued
  * on the context.

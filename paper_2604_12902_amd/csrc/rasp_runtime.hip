@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,7 +24,7 @@ constexpr int kTableRing = 16;
 constexpr uint64_t kStageWords = 32ull << 20;    // host-load staging: program + input words per chunk
 constexpr uint64_t kStageVms = 1ull << 20;       // and machines per chunk
 
-inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+constexpr uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 // First-fit allocator over [0, size) with coalescing free list.
 class Arena {
@@ -178,6 +179,8 @@ struct rasp_ctx {
     std::vector<GraphEntry> graphs;
     // kernel timing (RASP_OPT_PROFILE)
     int64_t profile = 0;
+    bool no_events = false;              // set while rasp_run_noalloc runs: no timing events
+    char *noalloc_scratch = nullptr;     // this device's no-allocation scratch (device address)
     struct Timed { int kind; hipEvent_t a, b; };
     std::vector<Timed> timed;
     std::vector<hipEvent_t> ev_pool;
@@ -273,7 +276,7 @@ hipEvent_t pooled_event(rasp_ctx *c)
 template <class F>
 hipError_t timed_launch(rasp_ctx *c, int kind, F fn)
 {
-    if (!c->profile) return fn();
+    if (!c->profile || c->no_events) return fn();
     hipEvent_t a = pooled_event(c), b = pooled_event(c);
     if (!a || !b) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(a, c->stream);
@@ -610,7 +613,16 @@ int mark_queued(rasp_ctx *c, Batch *b)
     return RASP_OK;
 }
 
-int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
+// Device memory a run needs beyond its batches: the queue counters, the
+// batch tables a launch reads and the survivor list of a first pass.
+struct RunScratch {
+    QueueState *queue;
+    BatchTable *table[2];                // the launch's table and, after a first pass, its successor
+    uint32_t *work;
+    uint64_t work_cap;                   // survivor-list entries
+};
+
+int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k, const RunScratch *rs = nullptr)
 {
     const uint32_t isa = bs[0]->dev.isa;
     for (uint32_t t = 1; t < k; ++t)
@@ -645,11 +657,14 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
             int rc = materialize(c, bs[t]);
             if (rc) return rc;
         }
-    const bool graphed = c->graph && !any_fresh;
+    // queue counters: the context's, or the caller-independent scratch
+    QueueState *const qs = rs ? rs->queue : c->queue;
+    const bool graphed = c->graph && !any_fresh && !rs;
     BatchTable *ht, *dt;
     int slot;
     int rc = table_slot(c, &ht, &dt, &slot);
     if (rc) return rc;
+    if (rs) dt = rs->table[0];
     std::memset(ht, 0, sizeof(BatchTable));
     uint64_t total = 0;
     uint32_t maxb = 0, max_n = 0, max_ell = 0;
@@ -682,11 +697,11 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
         HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
         HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
         c->table_used[slot] = true;
-        HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_zero_queue(c->queue, st); }));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_zero_queue(qs, st); }));
     }
     if (sched == RASP_SCHED_PLAIN && !graphed) {
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
-            return launch_plain(dt, total, maxb, isa, pow2, pack_in_plain, wm, nullptr, c->queue, st); }));
+            return launch_plain(dt, total, maxb, isa, pow2, pack_in_plain, wm, nullptr, qs, st); }));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
         return RASP_OK;
     }
@@ -722,18 +737,18 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
             uint32_t *work = (cap > 0 && cap < maxb) ? at<uint32_t>(c, c->work) : nullptr;
             hipGraph_t graph = nullptr;
             HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            hipError_t e = launch_zero_queue(c->queue, st);
+            hipError_t e = launch_zero_queue(qs, st);
             if (!e && cap > 0 && cap < maxb && lds_first) {
-                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, cap, work, c->queue, st);
-                if (!e) e = launch_reset_head(c->queue, st);
-                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st);
+                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, cap, work, qs, st);
+                if (!e) e = launch_reset_head(qs, st);
+                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st);
             } else if (!e && cap > 0 && cap < maxb) {
-                e = launch_plain(gt, total, cap, isa, pow2, false, wm, work, c->queue, st);
-                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st);
+                e = launch_plain(gt, total, cap, isa, pow2, false, wm, work, qs, st);
+                if (!e) e = launch_persistent(gt, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st);
             } else if (!e && cap >= maxb && !lds_first) {
-                e = launch_plain(gt, total, maxb, isa, pow2, false, wm, nullptr, c->queue, st);
+                e = launch_plain(gt, total, maxb, isa, pow2, false, wm, nullptr, qs, st);
             } else if (!e) {
-                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st);
+                e = launch_persistent(gt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st);
             }
             hipError_t e2 = hipStreamEndCapture(st, &graph);
             if (!e) e = e2;
@@ -751,18 +766,24 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
     if (fused) {
         // fresh batches present: one persistent launch over every machine
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st); }));
+            return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st); }));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     } else if (cap > 0 && cap < maxb) {
-        if ((rc = ensure_work(c, total))) return rc;
-        uint32_t *work = at<uint32_t>(c, c->work);
+        if (rs) {
+            if (total > rs->work_cap)
+                return fail(c, RASP_E_INVAL, "%llu machines exceed the survivor list of %llu entries",
+                            (unsigned long long)total, (unsigned long long)rs->work_cap);
+        } else if ((rc = ensure_work(c, total))) {
+            return rc;
+        }
+        uint32_t *work = rs ? rs->work : at<uint32_t>(c, c->work);
         if (lds_first) {
             HIPCHK(c, timed_launch(c, RASP_KERNEL_FIRST, [&] {
-                return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, cap, work, c->queue, st); }));
-            HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_reset_head(c->queue, st); }));
+                return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, cap, work, qs, st); }));
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_reset_head(qs, st); }));
         } else {
             HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
-                return launch_plain(dt, total, cap, isa, pow2, pack_in_plain, wm, work, c->queue, st); }));
+                return launch_plain(dt, total, cap, isa, pow2, pack_in_plain, wm, work, qs, st); }));
         }
         BatchTable *dt2 = dt;
         if (any_fresh) {
@@ -770,6 +791,7 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
             BatchTable *ht2;
             int slot2;
             if ((rc = table_slot(c, &ht2, &dt2, &slot2))) return rc;
+            if (rs) dt2 = rs->table[1];
             std::memcpy(ht2, ht, sizeof(BatchTable));
             for (uint32_t t = 0; t < k; ++t) ht2->b[t].fresh = 0;
             HIPCHK(c, hipMemcpyAsync(dt2, ht2, sizeof(BatchTable), hipMemcpyHostToDevice, st));
@@ -777,22 +799,60 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k)
             c->table_used[slot2] = true;
         }
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt2, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st); }));
+            return launch_persistent(dt2, total, work, cap, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st); }));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     } else if (cap >= maxb && !lds_first) {
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
-            return launch_plain(dt, total, maxb, isa, pow2, pack_in_plain, wm, nullptr, c->queue, st); }));
+            return launch_plain(dt, total, maxb, isa, pow2, pack_in_plain, wm, nullptr, qs, st); }));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     } else {
         // no first pass (or one as long as the budget): one persistent launch;
         // fresh machines here fit their slots and are built by the kernel
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
-            return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, c->queue, st); }));
+            return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st); }));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     }
     return RASP_OK;
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Scratch of rasp_run_noalloc: one fixed device array per GPU, held until the
+// process ends.  Layout: queue counters, two batch tables, then the survivor
+// list of up to kNoAllocMaxVms machines.  Host code never passes `scratch`
+// itself to a kernel or copy (in host code the name stands for a host-side
+// shadow, not a device address): each device's address is taken once, with
+// that device current, by hipGetSymbolAddress when a context is created on it.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint64_t kNoAllocMaxVms = 1ull << 22;
+constexpr uint64_t kNoAllocQueueOff = 0;
+constexpr uint64_t kNoAllocTableOff = align_up(sizeof(QueueState), kAlign);
+constexpr uint64_t kNoAllocWorkOff = kNoAllocTableOff + 2 * align_up(sizeof(BatchTable), kAlign);
+constexpr uint64_t kNoAllocBytes = kNoAllocWorkOff + 4 * kNoAllocMaxVms;
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+char *g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+// this device's address of `scratch` (the device must be current)
+hipError_t noalloc_scratch_of(int device, char **out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_noalloc_ptr[device] = static_cast<char *>(ptr);
+    }
+    *out = g_noalloc_ptr[device];
+    return hipSuccess;
+}
 }  // namespace
 
 // ===========================================================================
@@ -843,6 +903,12 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     c->arena_bytes = arena_bytes;
     c->alloc.reset(arena_bytes);
     init_kernel_attributes();
+    e = noalloc_scratch_of(device, &c->noalloc_scratch);
+    if (e) {
+        if (c->own_arena) (void)hipFree(c->arena);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        return fail(nullptr, RASP_E_DEVICE, "no-allocation scratch address: %s", hipGetErrorString(e));
+    }
     const uint64_t sbytes = align_up(sizeof(QueueState), kAlign) + (kTableRing + 1) * align_up(sizeof(BatchTable), kAlign);
     bool ok = arena_alloc(c.get(), sbytes, &c->scratch);
     if (ok) {
@@ -1063,6 +1129,37 @@ int rasp_run_multi(rasp_ctx *c, const rasp_batch *hs, const uint64_t *budgets, u
     for (uint32_t t = 0; t < k; ++t)
         if ((rc = mark_queued(c, bs[t]))) return rc;
     return RASP_OK;
+}
+
+int rasp_run_noalloc(rasp_ctx *c, rasp_batch h, uint64_t budget)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Batch *b = find(c, h);
+    if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
+    if (b->N > kNoAllocMaxVms)
+        return fail(c, RASP_E_INVAL, "rasp_run_noalloc takes at most %llu machines; the batch has %llu",
+                    (unsigned long long)kNoAllocMaxVms, (unsigned long long)b->N);
+    if (!c->noalloc_scratch) return fail(c, RASP_E_DEVICE, "no-allocation scratch is not available");
+    RunScratch rs;
+    rs.queue = reinterpret_cast<QueueState *>(c->noalloc_scratch + kNoAllocQueueOff);
+    rs.table[0] = reinterpret_cast<BatchTable *>(c->noalloc_scratch + kNoAllocTableOff);
+    rs.table[1] = reinterpret_cast<BatchTable *>(c->noalloc_scratch + kNoAllocTableOff + align_up(sizeof(BatchTable), kAlign));
+    rs.work = reinterpret_cast<uint32_t *>(c->noalloc_scratch + kNoAllocWorkOff);
+    rs.work_cap = kNoAllocMaxVms;
+    // budgets above 2^31 - 1 are applied in several launches (runs compose)
+    uint64_t left = budget;
+    c->no_events = true;
+    while (left > 0 && rc == RASP_OK) {
+        const uint32_t b32 = static_cast<uint32_t>(std::min<uint64_t>(left, 0x7fffffffull));
+        left -= b32;
+        rc = run_batches(c, &b, &b32, 1, &rs);
+    }
+    c->no_events = false;
+    // the batch's completion event was created by its load: recording it
+    // allocates nothing
+    if (rc == RASP_OK && b->done) HIPCHK(c, hipEventRecord(b->done, c->stream));
+    return rc;
 }
 
 int rasp_poll(rasp_ctx *c, rasp_batch h, int *done)

@@ -39,7 +39,7 @@ RASP_OPT_FIRST_PASS_KIND = 8
 KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other", "first")
 
 EXPORTED = ("rasp_create", "rasp_create_on_cus", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
-            "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi",
+            "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi", "rasp_run_noalloc",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
             "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
             "rasp_kernel_times", "rasp_running_counts", "rasp_autotune")
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(u64)], i32),
         "rasp_run": ([P, u64, u64], i32),
         "rasp_run_multi": ([P, P, P, u32], i32),
+        "rasp_run_noalloc": ([P, u64, u64], i32),
         "rasp_poll": ([P, u64, ctypes.POINTER(i32)], i32),
         "rasp_sync": ([P, u64], i32),
         "rasp_fetch_outputs": ([P, u64, ctypes.POINTER(rasp_outputs)], i32),
@@ -224,6 +225,10 @@ def rasp_load_state(ctx, desc: Desc, state: dict) -> int:
 
 def rasp_run(ctx, batch: int, budget: int) -> None:
     _check(_lib.rasp_run(ctx, batch, budget), ctx)
+
+
+def rasp_run_noalloc(ctx, batch: int, budget: int) -> None:
+    _check(_lib.rasp_run_noalloc(ctx, batch, budget), ctx)
 
 
 def rasp_run_multi(ctx, batches, budgets) -> None:

@@ -74,6 +74,12 @@ def parse():
     ap.add_argument("--epoch", type=int, default=None)
     ap.add_argument("--waves-per-cu", type=int, default=None)
     ap.add_argument("--first-pass-kind", type=int, default=None, choices=[0, 1])
+    ap.add_argument("--hot-cells", type=int, default=None, choices=[0, 8, 16, 32, 64],
+                    help="slots of the hot-cell LDS table per machine (0: off)")
+    ap.add_argument("--profile-steps", type=int, default=None,
+                    help="transitions profiled at the end of a hot-cell first pass")
+    ap.add_argument("--misfit-waves", type=int, default=None,
+                    help="waves per CU of the hot-cell misfits' launch")
     ap.add_argument("--inflight", type=int, default=0,
                     help="the headline times the persistent schedule with this many batches in "
                          "flight, one context, stream and host thread each (1: one batch at a "
@@ -267,6 +273,24 @@ def measured_traffic(workload: str, kernel: str, knobs: dict):
                            kernel)
 
 
+def TUNED_OPTIONS(R):
+    """The context options the autotuner chooses (copied to in-flight contexts)."""
+    return (R.RASP_OPT_SCHEDULE, R.RASP_OPT_LDS_WORDS, R.RASP_OPT_FIRST_PASS, R.RASP_OPT_EPOCH,
+            R.RASP_OPT_WAVES_PER_CU, R.RASP_OPT_FIRST_PASS_KIND, R.RASP_OPT_HOT_CELLS,
+            R.RASP_OPT_PROFILE_STEPS, R.RASP_OPT_MISFIT_WAVES)
+
+
+def current_knobs(R, ctx, lazy):
+    """The knobs of a run, as recorded beside traffic measurements."""
+    return dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
+                first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
+                waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
+                first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)),
+                hot_cells=int(ctx.get(R.RASP_OPT_HOT_CELLS)),
+                profile_steps=int(ctx.get(R.RASP_OPT_PROFILE_STEPS)),
+                misfit_waves=int(ctx.get(R.RASP_OPT_MISFIT_WAVES)), c0_in_run=lazy)
+
+
 # batches in flight tried (five to eight were slower on plain-scale)
 INFLIGHT_CANDIDATES = (1, 2, 4)
 # knobs tried again once several batches are in flight: the ones whose best
@@ -304,8 +328,7 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
     for c in ctxs:
         if c is ctx:
             continue
-        for o in (R.RASP_OPT_SCHEDULE, R.RASP_OPT_LDS_WORDS, R.RASP_OPT_FIRST_PASS, R.RASP_OPT_EPOCH,
-                  R.RASP_OPT_WAVES_PER_CU, R.RASP_OPT_FIRST_PASS_KIND):
+        for o in TUNED_OPTIONS(R):
             c.set(o, ctx.get(o))
     dev = torch.device("cuda", 0)
     N = batch.N
@@ -383,11 +406,7 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
     for c in ctxs:
         if c is not ctx:
             c.close()
-    knobs = dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
-                 first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
-                 waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
-                 first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=args.lazy,
-                 batches_in_flight=n, cu_partition=args.inflight_cus)
+    knobs = dict(current_knobs(R, ctx, args.lazy), batches_in_flight=n, cu_partition=args.inflight_cus)
     res = {"batches_in_flight": n, "cus": args.inflight_cus, "value": total_steps / (wall / steps),
            "ms_per_step": 1e3 * wall / steps,
            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
@@ -503,6 +522,9 @@ def main():
             ctx.set(R.RASP_OPT_EPOCH, tuned["epoch"])
             ctx.set(R.RASP_OPT_WAVES_PER_CU, tuned["waves_per_cu"])
             ctx.set(R.RASP_OPT_FIRST_PASS_KIND, tuned["first_pass_kind"])
+            ctx.set(R.RASP_OPT_HOT_CELLS, tuned.get("hot_cells", 0))
+            ctx.set(R.RASP_OPT_PROFILE_STEPS, tuned.get("profile_steps", 256))
+            ctx.set(R.RASP_OPT_MISFIT_WAVES, tuned.get("misfit_waves", 6))
         ctx.set(R.RASP_OPT_SCHEDULE, schedule)
         if args.first_pass is not None:
             ctx.set(R.RASP_OPT_FIRST_PASS, args.first_pass)
@@ -514,6 +536,12 @@ def main():
             ctx.set(R.RASP_OPT_WAVES_PER_CU, args.waves_per_cu)
         if args.first_pass_kind is not None:
             ctx.set(R.RASP_OPT_FIRST_PASS_KIND, args.first_pass_kind)
+        if args.hot_cells is not None:
+            ctx.set(R.RASP_OPT_HOT_CELLS, args.hot_cells if schedule == R.RASP_SCHED_PERSISTENT else 0)
+        if args.profile_steps is not None:
+            ctx.set(R.RASP_OPT_PROFILE_STEPS, args.profile_steps)
+        if args.misfit_waves is not None:
+            ctx.set(R.RASP_OPT_MISFIT_WAVES, args.misfit_waves)
 
     def one_step(keep=False):
         h = R.rasp_load_batch(ctx.handle, desc)
@@ -563,10 +591,7 @@ def main():
         if name == "plain" and args.no_plain:
             continue
         wall, per, kt = timed(sched)
-        knobs = dict(schedule=int(ctx.get(R.RASP_OPT_SCHEDULE)), lds_words=int(ctx.get(R.RASP_OPT_LDS_WORDS)),
-                     first_pass=int(ctx.get(R.RASP_OPT_FIRST_PASS)), epoch=int(ctx.get(R.RASP_OPT_EPOCH)),
-                     waves_per_cu=int(ctx.get(R.RASP_OPT_WAVES_PER_CU)),
-                     first_pass_kind=int(ctx.get(R.RASP_OPT_FIRST_PASS_KIND)), c0_in_run=args.lazy)
+        knobs = current_knobs(R, ctx, args.lazy)
         if args.verify != "none":
             verify()
         ms = 1e3 * wall / args.steps
@@ -614,7 +639,8 @@ def main():
         # unless another is at least 3% faster); a knob given on the command
         # line is kept.
         retune = []
-        if args.first_pass is None:
+        # (a hot-cell first pass is as long as its profile needs: kept)
+        if args.first_pass is None and int(ctx.get(R.RASP_OPT_HOT_CELLS)) == 0:
             retune.append(("first pass", R.RASP_OPT_FIRST_PASS, INFLIGHT_FIRST_PASSES))
         if args.epoch is None:
             retune.append(("epoch", R.RASP_OPT_EPOCH, INFLIGHT_EPOCHS))
@@ -644,9 +670,15 @@ def main():
     # run was asked for (one: results["persistent"])
     head = inflight if inflight is not None else results["persistent"]
     kt = head["kernels"]
-    # dominant kernel of the headline schedule: largest total time
+    # dominant kernel of the headline schedule: largest total time; with
+    # hot-cell tables the fits' and the misfits' launches run side by side
+    # over the survivors of the first pass, and count as one (their common
+    # span is the longer of the two)
     dom = max((k for k in kt if kt[k][1] > 0), key=lambda k: kt[k][0])
     dom_ms = kt[dom][0] / kt[dom][1]
+    if kt.get("misfit", (0, 0))[1] and kt["persistent"][1] and dom in ("persistent", "misfit"):
+        dom = "persistent+misfit"
+        dom_ms = max(kt["persistent"][0] / kt["persistent"][1], kt["misfit"][0] / kt["misfit"][1])
     fp_pass = head["knobs"]["first_pass"]
     # which launch built c0: the pack kernel, the first pass (plain or LDS
     # persistent kernel) or the persistent kernel itself
@@ -669,7 +701,7 @@ def main():
     elif dom == "persistent" and c0_in == "persistent":
         algo = pack_bytes(batch) + bstep * total_steps + 25.0 * N
         unit_note = "%s + %.2f B per retired step + 25 B final state per machine" % (c0_note, bstep)
-    elif dom == "persistent":
+    elif dom in ("persistent", "persistent+misfit"):
         algo = bstep * (total_steps - steps_first) + 50.0 * int((ref.steps > fp_pass).sum())
         unit_note = "%.2f B per retired step x steps retired by the launch + 50 B state per machine" % bstep
     else:

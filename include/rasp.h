@@ -324,6 +324,21 @@ int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
  *                          persistent kernel with every machine's memory in
  *                          its LDS slot, when every memory fits a slot
  *                          (otherwise the plain kernel)
+ *   RASP_OPT_HOT_CELLS     persistent schedule with a plain first pass, memories
+ *                          of at most 2,048 words: 0 (default) off; S in
+ *                          {8, 16, 32, 64}: the first pass profiles the 2-word
+ *                          cells each machine touches in its last
+ *                          RASP_OPT_PROFILE_STEPS transitions, and the persistent
+ *                          kernel keeps a machine's profiled cells (up to S,
+ *                          hashed into S slots) in LDS, every other word in HBM
+ *                          (replaces RASP_OPT_LDS_WORDS for that launch)
+ *   RASP_OPT_PROFILE_STEPS transitions profiled at the end of a hot-cell first
+ *                          pass, >= 1 (default 256)
+ *   RASP_OPT_MISFIT_WAVES  resident waves per compute unit of the launch that
+ *                          runs the survivors of a hot-cell first pass whose
+ *                          cells do not fit (memory in HBM, on a second stream
+ *                          of the context beside the fits' launch), 1..32
+ *                          (default 6)
  */
 enum {
     RASP_OPT_SCHEDULE = 1,
@@ -332,7 +347,10 @@ enum {
     RASP_OPT_WAVES_PER_CU = 4,
     RASP_OPT_GRAPH = 5,
     RASP_OPT_FIRST_PASS = 6,
-    RASP_OPT_FIRST_PASS_KIND = 8
+    RASP_OPT_FIRST_PASS_KIND = 8,
+    RASP_OPT_HOT_CELLS = 9,
+    RASP_OPT_PROFILE_STEPS = 10,
+    RASP_OPT_MISFIT_WAVES = 11
 };
 enum { RASP_SCHED_AUTO = 0, RASP_SCHED_PLAIN = 1, RASP_SCHED_PERSISTENT = 2 };
 
@@ -353,7 +371,8 @@ enum {
     RASP_KERNEL_DIGEST = 3,        /* memory digests                            */
     RASP_KERNEL_OTHER = 4,         /* checks, scans, copies, queue reset        */
     RASP_KERNEL_FIRST = 5,         /* work-queue first pass with LDS memory     */
-    RASP_KERNEL_COUNT = 6
+    RASP_KERNEL_MISFIT = 6,        /* hot-cell misfits' work-queue step loop    */
+    RASP_KERNEL_COUNT = 7
 };
 enum { RASP_OPT_PROFILE = 7 };
 int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
@@ -363,11 +382,14 @@ int rasp_kernel_times(rasp_ctx *ctx, double *ms, uint64_t *launches);
  * Copies the first min(num_vms, max_vms) machines of b into a scratch batch
  * (b itself is not changed), then times rasp_run(budget) on fresh copies of
  * that snapshot while searching one knob at a time (LDS words per machine,
- * first-pass length, epoch, waves per compute unit, first-pass kind;
- * persistent schedule against plain), keeps the fastest setting in the
- * context and writes it to chosen[0..5] = {schedule, lds_words, first_pass,
- * epoch, waves_per_cu, first_pass_kind} (chosen may be NULL); a knob leaves
- * its current setting only for a setting at least 3% faster.  Returns the
+ * first-pass length, epoch, waves per compute unit, first-pass kind), then
+ * hot-cell tables (slots per machine and misfit waves per CU on a grid, then
+ * the profile length) when memories have at most 2,048 words, and the plain
+ * schedule; keeps the fastest setting in the context and writes it to
+ * chosen[0..8] = {schedule, lds_words, first_pass, epoch, waves_per_cu,
+ * first_pass_kind, hot_cells, profile_steps, misfit_waves} (chosen may be
+ * NULL); a knob leaves its current setting only for a setting at least 3%
+ * faster.  Returns the
  * best time in *best_ms (may be NULL).  A lazily loaded batch stays lazy:
  * each trial builds c0 of the prefix again from the descriptor.
  * Errors: STATE, NOMEM (no room for the snapshot), DEVICE.

@@ -53,33 +53,42 @@ def per_dispatch(d, counter):
 def measure(fdir, wdir, nbytes, ksub, last=0):
     """Bytes per launch of the kernels whose name contains `ksub`: the mean
     over their dispatches, or over the `last` latest ones (a run that times
-    two modes one after the other)."""
+    two modes one after the other).  `ksub` may list several substrings
+    separated by '|' (launches that run side by side as one step, such as
+    the fits' and the misfits' launches of a hot-cell run): the result is the
+    sum of their per-launch means."""
     res = {"copy_bytes": nbytes, "kernel": ksub}
     if last:
         res["last_dispatches"] = last
+    parts = ksub.split("|")
     for tag, d, c in (("fetch", fdir, "FETCH_SIZE"), ("write", wdir, "WRITE_SIZE")):
         vals = per_dispatch(d, c)
         copies = [v for (n, _), v in vals.items() if "copyBuffer" in n]
-        kern = [v for (n, disp), v in sorted(vals.items(), key=lambda e: e[0][1]) if ksub in n]
-        if last:
-            kern = kern[-last:]
         ref = max(copies)
         scale = nbytes / (ref * 1024.0)
         res[tag + "_copy_kib"] = ref
         res[tag + "_scale"] = scale
-        res[tag + "_kernel_kib_mean"] = sum(kern) / len(kern)
-        res[tag + "_kernel_dispatches"] = len(kern)
-        res[tag + "_bytes_per_launch"] = sum(kern) / len(kern) * 1024.0 * scale
+        kib = 0.0
+        for part in parts:
+            kern = [v for (n, disp), v in sorted(vals.items(), key=lambda e: e[0][1]) if part in n]
+            if last:
+                kern = kern[-last:]
+            kib += sum(kern) / len(kern)
+            res[tag + "_kernel_dispatches"] = len(kern)
+        res[tag + "_kernel_kib_mean"] = kib
+        res[tag + "_bytes_per_launch"] = kib * 1024.0 * scale
     res["bytes_per_launch"] = res["fetch_bytes_per_launch"] + res["write_bytes_per_launch"]
     return res
 
 
 # the knobs that can change the bytes a kernel moves per launch: k_pack runs
 # before any step (only how c0 is built and the CU share matter); the first
-# pass also depends on its length; the persistent kernel on every knob
+# pass also depends on its length and on whether it profiles hot cells; the
+# persistent kernels (and the hot-cell pair of launches) on every knob
 KNOBS_OF_KERNEL = {
     "pack": ("c0_in_run", "batches_in_flight", "cu_partition"),
-    "plain": ("first_pass", "first_pass_kind", "c0_in_run", "batches_in_flight", "cu_partition"),
+    "plain": ("first_pass", "first_pass_kind", "c0_in_run", "batches_in_flight", "cu_partition",
+              "hot_cells", "profile_steps"),
 }
 
 

@@ -59,6 +59,29 @@ struct QueueState {
     unsigned long long survivors;      // items appended to the survivor list
     unsigned long long retired;        // transitions retired (statistics)
     unsigned long long pad;
+    unsigned long long misfits;        // hot-cell first pass: survivors whose hot cells do not all fit
+    unsigned long long head_m;         // next unclaimed misfit
+    unsigned long long pad2[2];
+};
+
+// Hot-cell tables.  A first pass profiles the last R transitions of every
+// machine it leaves running: the 2-word cells (words 2x, 2x + 1) its
+// fetches and data accesses touch.  A survivor whose cells can be placed in
+// S slots without two sharing one (slot of cell x = bits [16, 16 + log2 S)
+// of x * c, c chosen per machine) is a fit; the persistent kernel then keeps
+// exactly those cells in LDS and every access of its steady loop is an LDS
+// hit.  Fit p of the survivor list has multiplier mult[p] and cells
+// tags[p S + s] (0xffff: empty slot); misfits go to a list of their own
+// (count q->misfits), run with their memory in HBM by a second persistent
+// launch beside the fits' launch, so that no wave mixes the two.
+struct HotArgs {
+    uint32_t S;                        // slots per machine (power of two, 8..64); 0: off
+    uint32_t lgS;
+    uint32_t R;                        // profiled transitions at the end of the first pass
+    uint32_t bw;                       // profile bitmap words per lane
+    uint32_t *mult;
+    uint16_t *tags;
+    uint32_t *mis;                     // misfit list
 };
 
 // Descriptor-check error bits.
@@ -99,14 +122,27 @@ hipError_t launch_probe(DevBatch b, hipStream_t st);
 // wm: some batch of the launch has words narrower than 32 bits
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap,
                         uint32_t isa, bool pow2, bool pack, bool wm, uint32_t *surv, QueueState *q,
-                        hipStream_t st);
+                        hipStream_t st, const HotArgs *hot = nullptr);
 // cap < UINT32_MAX with surv non-null: a first pass (machines still running
 // after cap transitions are appended to surv, q->survivors counts them)
 hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32_t *work,
                              uint32_t already, uint32_t isa, bool pow2, bool wm, uint32_t epoch,
                              uint32_t lds_words, uint32_t max_n, uint32_t max_ell,
                              uint32_t waves_per_block, uint32_t blocks, uint32_t cap, uint32_t *surv,
-                             QueueState *q, hipStream_t st);
+                             QueueState *q, hipStream_t st, bool misfits = false);
+// (misfits: the work list is a hot-cell first pass's misfit list, counted by
+// q->misfits and claimed through q->head_m)
+// the persistent kernel over the fits of a hot-cell first pass, each
+// machine's hot cells in its lane's LDS table
+hipError_t launch_persistent_hot(const BatchTable *tab, const uint32_t *work, uint32_t already, uint32_t isa,
+                                 bool pow2, bool wm, uint32_t epoch, const HotArgs &hot,
+                                 uint32_t waves_per_block, uint32_t blocks, QueueState *q, hipStream_t st);
+// LDS words per lane of a hot-cell table of S slots (two words and a 16-bit
+// cell tag per slot)
+constexpr uint32_t hot_slot_words(uint32_t S) { return 2u * S + S / 2u; }
+// profile bitmap words per lane for memories of at most max_n words
+constexpr uint32_t hot_bitmap_words(uint32_t max_n) { return ((max_n + 1u) / 2u + 31u) / 32u; }
+constexpr uint32_t kHotMaxN = 2048;     // largest memory a hot-cell launch profiles
 // err |= kErrWordRange if some of the `count` words is not a w-bit value
 hipError_t launch_check_words(const int32_t *w, uint64_t count, uint32_t wshift, uint32_t *err,
                               hipStream_t st);

@@ -92,6 +92,7 @@ __device__ __forceinline__ const gi32 *gptr(const int32_t *p) { return (const gi
 struct GlobalMem {                       // every word in HBM
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
+    static constexpr bool kHot = false;
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
     __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
@@ -116,6 +117,7 @@ struct GlobalMem {                       // every word in HBM
 struct LdsMem {                          // whole memory in the lane's LDS slot (n <= P)
     static constexpr bool kLds = true;
     static constexpr bool kColdIO = false;
+    static constexpr bool kHot = false;
     uint32_t base;                       // word index of the slot in rasp_lds
     uint32_t spare;                      // word index of the slot's spare word
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
@@ -143,6 +145,7 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     // word at or above P or needs the general positions, and lays all of
     // that out of line
     static constexpr bool kColdIO = true;
+    static constexpr bool kHot = false;
     uint32_t base, P;
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const
@@ -184,6 +187,108 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
         const int32_t *const pn = &rasp_lds[base + np];
         o = pn[0];
         j = pn[1];
+    }
+};
+
+// Hot-cell slot of cell x (words 2x, 2x + 1) for multiplier c: bits
+// [16, 16 + log2 S) of x * c (cells are below 2^10, c at most 2^16, so a
+// 24-bit multiply is exact); c = 2^16 places consecutive cells in
+// consecutive slots
+__device__ __forceinline__ uint32_t hot_slot(uint32_t x, uint32_t c, uint32_t mask)
+{
+    return (__umul24(x, c) >> 16) & mask;
+}
+
+// the multiplier tried `k`-th when a profiled machine's cells are placed
+__device__ __forceinline__ uint32_t hot_mult(uint32_t k)
+{
+    return k == 0 ? 65536u : (((k * 0x9E3779B1u) >> 16) | 1u);
+}
+constexpr uint32_t kHotCandidates = 64;
+
+// every word in HBM, and every cell an access touches marked in the lane's
+// profile bitmap (LDS, bit x of the bitmap = cell x; word k of a thread's
+// bitmap at bm + k * stride): the fetched cell, and the data cell when the
+// transition stores or reads its data word
+struct ProfMem {
+    static constexpr bool kLds = false;
+    static constexpr bool kColdIO = false;
+    static constexpr bool kHot = false;
+    gi32 *M;
+    uint32_t bm, stride;
+    __device__ __forceinline__ void mark(uint32_t k) const
+    {
+        const uint32_t x = k >> 1;
+        atomicOr(reinterpret_cast<uint32_t *>(&rasp_lds[bm + (x >> 5) * stride]), 1u << (x & 31u));
+    }
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
+    __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
+                                         uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        mark(np);
+        mark(nq);
+        if (st_en | need) mark(jj);
+        if (st_en) M[jj] = w;
+        d = 0;
+        if (need) d = M[jj];
+        o = M[np];
+        j = M[nq];
+    }
+};
+
+// A machine's hot cells in its lane's LDS table, every other word in HBM.
+// Slot s of lane l: its two words at word wb + 128 s (wb = wave base + 2 l),
+// its cell tag (uint16, 0xffff: empty) at halfword tb + 64 s (tb = tag
+// base + l): the 64 lanes of a wave read one slot each without bank
+// conflicts whatever slots they pick.  The LDS copy of a tagged cell is the
+// machine's word; HBM holds it again only after the write-back.
+struct HotMem {
+    static constexpr bool kLds = false;
+    static constexpr bool kColdIO = false;
+    static constexpr bool kHot = true;
+    uint32_t wb, tb, c, mask;
+    gi32 *M;
+    __device__ __forceinline__ uint32_t slot(uint32_t x) const { return hot_slot(x, c, mask); }
+    __device__ __forceinline__ uint32_t tag(uint32_t s) const
+    {
+        return reinterpret_cast<const uint16_t *>(rasp_lds)[tb + 64u * s];
+    }
+    __device__ __forceinline__ int2 pair(uint32_t s) const
+    {
+        return *reinterpret_cast<const int2 *>(&rasp_lds[wb + 128u * s]);
+    }
+    __device__ __forceinline__ void put(uint32_t s, uint32_t half, int32_t v) const
+    {
+        rasp_lds[wb + 128u * s + half] = v;
+    }
+    __device__ __forceinline__ int32_t ld(uint32_t k) const
+    {
+        const uint32_t x = k >> 1, s = slot(x);
+        int32_t v;
+        if (tag(s) == x) v = rasp_lds[wb + 128u * s + (k & 1u)]; else v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
+    {
+        const uint32_t x = k >> 1, s = slot(x);
+        int32_t v = 0;
+        if (tag(s) == x) v = rasp_lds[wb + 128u * s + (k & 1u)]; else if (need) v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
+    {
+        const uint32_t x = k >> 1, s = slot(x);
+        if (en) { if (tag(s) == x) put(s, k & 1u, v); else M[k] = v; }
+    }
+    // each access looks its cell up on its own (general positions, a
+    // misaligned fetch, an operand that wraps, or cells not in the table)
+    __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
+                                         uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        st(jj, w, st_en);
+        d = ld_data(jj, need);
+        o = ld(np);
+        j = ld(nq);
     }
 };
 
@@ -315,7 +420,15 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             // jj = j only for j in [0, n); with w < 32 a jump target j < n can
             // also be the largest word, whose operand position i + 1 wraps.
             // (A split slot tests its lanes below, with its uncommon work.)
-            if constexpr (!Mem::kColdIO) {
+            if constexpr (Mem::kHot) {
+                // as in the split slot: an operand outside [0, n) needs the
+                // general positions only for a lane that uses its data word
+                // or jumps to it (a LOAD immediate or a jump not taken does
+                // not); every position a hot-cell lookup takes is masked to
+                // its table, so the other lanes' raw operands are harmless
+                rare = ((static_cast<uint32_t>(j) >= n) & (st_en | need | taken)) | (i >= imax - 3) | (n < 2u);
+                if (WM) rare |= taken & (j >= imax - 3);
+            } else if constexpr (!Mem::kColdIO) {
                 rare = (static_cast<uint32_t>(j) >= n) | (i >= imax - 3) | (n < 2u);
                 if (WM) rare |= j >= imax - 3;
             }
@@ -362,6 +475,43 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
                 if (Tape::kLds) w = rd_ok ? tv : a;
                 mem.step_near(jx, w, st_en, np, d, o, j);
             }
+        } else if constexpr (Mem::kHot) {
+            // the data cell (the fetched cell again for a lane without a data
+            // access) and the next instruction's cell are read with their
+            // tags; every lane hitting both, with an aligned fetch whose
+            // operand does not wrap and nothing else uncommon, takes the
+            // straight LDS step
+            // lanes that use an operand outside [0, n) take their Euclidean
+            // positions first (one wave-uniform test); the cells they name
+            // are then looked up like any other
+            if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();
+            const uint32_t jx = (st_en | need) ? jj : np;
+            const uint32_t cf = np >> 1, cd = jx >> 1;
+            const uint32_t sf = mem.slot(cf), sd = mem.slot(cd);
+            const int2 ef = mem.pair(sf), ed = mem.pair(sd);
+            // the common step reads the next instruction as one cell: an
+            // aligned np whose operand is word np + 1 (not wrapped to word 0
+            // or moved by i wrapping at the largest word)
+            bool cold = app | ((np & 1u) != 0u) | (nq != np + 1u) | (mem.tag(sf) != cf) | (mem.tag(sd) != cd);
+            if (!Tape::kLds) cold |= rd_ok;
+            // the slot reads stay beside the tag reads (one LDS round trip a
+            // step) instead of sinking behind the test below, their only use
+            __asm__ volatile("" : : "v"(ef.x), "v"(ef.y), "v"(ed.x), "v"(ed.y));
+            if (__builtin_expect(any_lane(cold), 0)) {
+                if (Tape::kLds) w = rd_ok ? tv : a;
+                else if (rd_ok) w = tape.ld(u0);
+                mem.step(jj, w, st_en, need, np, nq, d, o, j);
+                out.st(y0, d, app);
+            } else {
+                if (Tape::kLds) w = rd_ok ? tv : a;
+                const uint32_t half = jx & 1u;
+                if (st_en) mem.put(sd, half, w);
+                d = half ? ed.y : ed.x;
+                // a store into the next instruction's cell is seen by its fetch
+                const bool same = st_en & (sd == sf);
+                o = (same & (half == 0u)) ? w : ef.x;
+                j = (same & (half != 0u)) ? w : ef.y;
+            }
         } else {
             if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();
             if (Tape::kLds) w = rd_ok ? tv : a;                // loaded one step ahead
@@ -377,7 +527,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         if (WM) na = static_cast<uint32_t>(sext(na, ws));
         na = op == 1u ? static_cast<uint32_t>(jcur) : na;
         a = static_cast<int32_t>(na);
-        if (!Mem::kColdIO) out.st(y0, d, app);
+        if constexpr (!Mem::kColdIO && !Mem::kHot) out.st(y0, d, app);
         y0 += app ? 1u : 0u;
         i = ni;
         p = np;
@@ -545,12 +695,89 @@ hipError_t launch_probe(DevBatch b, hipStream_t st)
 // Every lane runs its machine for at most `cap` transitions.  With cap below
 // the batch budget, machines still running are appended (wave-aggregated
 // atomic) to the survivor list for the persistent kernel.
+// PROF (a hot-cell first pass): the last hot.R transitions mark the cells
+// they touch in the thread's LDS bitmap; a survivor then looks for a
+// multiplier that gives each of its cells a slot of its own among hot.S
+// (the first of kHotCandidates that does), and is listed as a fit (count
+// q->survivors) with that multiplier and its cells, or on the misfit list
+// (count q->misfits).
 // ---------------------------------------------------------------------------
 
-template <int ISA, bool POW2, bool PACK>
+// wave-aggregated append of the lanes with `mine` set to a list: one atomic
+// per wave; returns the lane's rank-th entry index
+__device__ __forceinline__ uint64_t wave_append(bool mine, unsigned long long *counter, uint32_t lane)
+{
+    const uint64_t mask = __ballot(mine);
+    unsigned long long base = 0;
+    if (mask) {
+        const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+        if (lane == static_cast<uint32_t>(leader))
+            base = atomicAdd(counter, static_cast<unsigned long long>(__popcll(mask)));
+        base = __shfl(base, leader);
+    }
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// whether the survivor's profiled cells (bitmap words bm + k * stride,
+// k < bw) fit a table: at most hot.S cells and a multiplier c_out that
+// places each in a slot of its own
+__device__ __forceinline__ bool hot_place(uint32_t bm, uint32_t stride, const HotArgs &hot, uint32_t &c_out)
+{
+    const uint32_t mask = hot.S - 1u;
+    uint32_t h = 0;
+    for (uint32_t k = 0; k < hot.bw; ++k) h += __popc(static_cast<uint32_t>(rasp_lds[bm + k * stride]));
+    c_out = 65536u;
+    if (h > hot.S) return false;
+    for (uint32_t cand = 0; cand < kHotCandidates; ++cand) {
+        const uint32_t c = hot_mult(cand);
+        uint64_t occ = 0;
+        bool ok = true;
+        for (uint32_t k = 0; k < hot.bw && ok; ++k) {
+            uint32_t w = static_cast<uint32_t>(rasp_lds[bm + k * stride]);
+            while (w != 0u && ok) {
+                const uint32_t x = 32u * k + static_cast<uint32_t>(__builtin_ctz(w));
+                w &= w - 1u;
+                const uint64_t bit = 1ull << hot_slot(x, c, mask);
+                ok = (occ & bit) == 0;
+                occ |= bit;
+            }
+        }
+        if (ok) {
+            c_out = c;
+            return true;
+        }
+    }
+    return false;
+}
+
+// write fit p's table: the multiplier and, per slot, its cell or 0xffff
+__device__ __forceinline__ void hot_write(uint32_t bm, uint32_t stride, const HotArgs &hot, uint64_t p,
+                                          uint32_t c)
+{
+    const uint32_t mask = hot.S - 1u;
+    uint16_t *tg = hot.tags + p * hot.S;
+    uint64_t occ = 0;
+    for (uint32_t k = 0; k < hot.bw; ++k) {
+        uint32_t w = static_cast<uint32_t>(rasp_lds[bm + k * stride]);
+        while (w != 0u) {
+            const uint32_t x = 32u * k + static_cast<uint32_t>(__builtin_ctz(w));
+            w &= w - 1u;
+            const uint32_t sl = hot_slot(x, c, mask);
+            if (((occ >> sl) & 1ull) == 0) {
+                occ |= 1ull << sl;
+                tg[sl] = static_cast<uint16_t>(x);
+            }
+        }
+    }
+    for (uint32_t sl = 0; sl < hot.S; ++sl)
+        if (((occ >> sl) & 1ull) == 0) tg[sl] = 0xffffu;
+    hot.mult[p] = c;
+}
+
+template <int ISA, bool POW2, bool PACK, bool PROF>
 __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ tab, uint64_t total,
                                                uint32_t cap, uint32_t wm, uint32_t *__restrict__ surv,
-                                               QueueState *__restrict__ q)
+                                               QueueState *__restrict__ q, HotArgs hot)
 {
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -626,8 +853,22 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             TapeG tg{gptr(b.T + b.t_off[v])};
             bool halted;
             const OutG og{gptr(b.Y + b.y_off[v])};
-            const uint32_t t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, b.wshift)
-                                  : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, 0u);
+            uint32_t t;
+            if constexpr (PROF) {
+                // the last min(R, limit) transitions are profiled
+                for (uint32_t kk = 0; kk < hot.bw; ++kk) rasp_lds[threadIdx.x + kk * blockDim.x] = 0;
+                const uint32_t R = hot.R < limit ? hot.R : limit;
+                t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit - R, halted, b.wshift)
+                       : run_machine<ISA, POW2, false>(m, tg, r, og, limit - R, halted, 0u);
+                if (!halted && t == limit - R) {
+                    const ProfMem pm{gptr(b.M + b.mem_off[v]), threadIdx.x, blockDim.x};
+                    t += wm ? run_machine<ISA, POW2, true>(pm, tg, r, og, R, halted, b.wshift)
+                            : run_machine<ISA, POW2, false>(pm, tg, r, og, R, halted, 0u);
+                }
+            } else {
+                t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, b.wshift)
+                       : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, 0u);
+            }
             if (t || fresh) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
                 b.steps[v] = fresh ? t : b.steps[v] + t;
@@ -639,7 +880,18 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0; b.status[v] = 0;
         }
     }
-    if (surv != nullptr) {
+    if (PROF && surv != nullptr) {
+        uint32_t c = 65536u;
+        const bool fit = survive && hot_place(threadIdx.x, blockDim.x, hot, c);
+        const uint64_t pf = wave_append(fit, &q->survivors, lane);
+        const uint64_t pm = wave_append(survive && !fit, &q->misfits, lane);
+        if (fit) {
+            surv[pf] = static_cast<uint32_t>(g);
+            hot_write(threadIdx.x, blockDim.x, hot, pf, c);
+        } else if (survive) {
+            hot.mis[pm] = static_cast<uint32_t>(g);
+        }
+    } else if (surv != nullptr) {
         const uint64_t mask = __ballot(survive);
         if (mask) {
             const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
@@ -657,23 +909,31 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
 
 template <int ISA, bool POW2>
 static void plain_go(bool pack, unsigned blocks, hipStream_t st, const BatchTable *tab, uint64_t total,
-                     uint32_t cap, uint32_t wm, uint32_t *surv, QueueState *q)
+                     uint32_t cap, uint32_t wm, uint32_t *surv, QueueState *q, const HotArgs *hot)
 {
-    if (pack) k_plain<ISA, POW2, true><<<blocks, 256, 0, st>>>(tab, total, cap, wm, surv, q);
-    else k_plain<ISA, POW2, false><<<blocks, 256, 0, st>>>(tab, total, cap, wm, surv, q);
+    if (hot) {
+        const size_t shmem = static_cast<size_t>(hot->bw) * 256u * sizeof(int32_t);
+        if (pack) k_plain<ISA, POW2, true, true><<<blocks, 256, shmem, st>>>(tab, total, cap, wm, surv, q, *hot);
+        else k_plain<ISA, POW2, false, true><<<blocks, 256, shmem, st>>>(tab, total, cap, wm, surv, q, *hot);
+        return;
+    }
+    const HotArgs none{};
+    if (pack) k_plain<ISA, POW2, true, false><<<blocks, 256, 0, st>>>(tab, total, cap, wm, surv, q, none);
+    else k_plain<ISA, POW2, false, false><<<blocks, 256, 0, st>>>(tab, total, cap, wm, surv, q, none);
 }
 
 hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uint32_t isa,
-                        bool pow2, bool pack, bool wm, uint32_t *surv, QueueState *q, hipStream_t st)
+                        bool pow2, bool pack, bool wm, uint32_t *surv, QueueState *q, hipStream_t st,
+                        const HotArgs *hot)
 {
     const unsigned blocks = static_cast<unsigned>((total + 255) / 256);
     const uint32_t w = wm ? 1u : 0u;
     if (isa == 1) {
-        if (pow2) plain_go<1, true>(pack, blocks, st, tab, total, cap, w, surv, q);
-        else plain_go<1, false>(pack, blocks, st, tab, total, cap, w, surv, q);
+        if (pow2) plain_go<1, true>(pack, blocks, st, tab, total, cap, w, surv, q, hot);
+        else plain_go<1, false>(pack, blocks, st, tab, total, cap, w, surv, q, hot);
     } else {
-        if (pow2) plain_go<0, true>(pack, blocks, st, tab, total, cap, w, surv, q);
-        else plain_go<0, false>(pack, blocks, st, tab, total, cap, w, surv, q);
+        if (pow2) plain_go<0, true>(pack, blocks, st, tab, total, cap, w, surv, q, hot);
+        else plain_go<0, false>(pack, blocks, st, tab, total, cap, w, surv, q, hot);
     }
     return hipGetLastError();
 }
@@ -724,7 +984,7 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
                                                 const uint32_t *__restrict__ work, uint32_t already,
                                                 uint32_t epoch, uint32_t P, uint32_t TL, uint32_t wm,
                                                 uint32_t cap, uint32_t *__restrict__ surv,
-                                                QueueState *__restrict__ q)
+                                                QueueState *__restrict__ q, uint32_t which)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = threadIdx.x / kWave;
@@ -732,7 +992,10 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
     const uint32_t SP = P + 4u + (TLDS ? TL : 0u);         // slot: memory, spares, tape
     const uint32_t wave_base = wib * kWave * SP;           // word index of lane 0's slot
     const uint32_t slot = wave_base + lane * SP;
-    if (work != nullptr) total = q->survivors;             // written by the first pass
+    // the survivor (or misfit) count written by the first pass, and the
+    // list's claim counter
+    if (work != nullptr) total = which ? q->misfits : q->survivors;
+    unsigned long long *const head = which ? &q->head_m : &q->head;
 
     bool has = false, exhausted = false, fresh = false, cut = false;
     Regs r{};
@@ -752,7 +1015,7 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
             const uint32_t cnt = __popcll(idle);
             unsigned long long base = 0;
             if (lane == static_cast<uint32_t>(leader))
-                base = __hip_atomic_fetch_add(&q->head, static_cast<unsigned long long>(cnt),
+                base = __hip_atomic_fetch_add(head, static_cast<unsigned long long>(cnt),
                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             base = __shfl(base, leader);
             if (base + cnt >= total) exhausted = true;
@@ -982,21 +1245,201 @@ __global__ __launch_bounds__(256) void k_persistent(const BatchTable *__restrict
                                                     uint32_t already, uint32_t epoch,
                                                     uint32_t P, uint32_t TL, uint32_t wm,
                                                     uint32_t cap, uint32_t *__restrict__ surv,
-                                                    QueueState *__restrict__ q)
+                                                    QueueState *__restrict__ q, uint32_t which)
 {
     if (tab->count == 1)
-        persistent_body<ISA, MODE, POW2, TLDS, true>(tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+        persistent_body<ISA, MODE, POW2, TLDS, true>(tab, total, work, already, epoch, P, TL, wm, cap, surv, q, which);
     else
-        persistent_body<ISA, MODE, POW2, TLDS, false>(tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+        persistent_body<ISA, MODE, POW2, TLDS, false>(tab, total, work, already, epoch, P, TL, wm, cap, surv, q, which);
+}
+
+// ---------------------------------------------------------------------------
+// K3 over the fits of a hot-cell first pass.  A claimed machine's table is
+// filled from its cell list and its memory; a finished machine's tagged
+// cells are written back.  Both are done by the whole wave, 64 / S machines
+// per instruction (lane k serves slot k mod S of the (k / S)-th machine of
+// the pass).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, uint32_t src)
+{
+    const uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(x)), static_cast<int>(src)));
+    const uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(static_cast<uint32_t>(x >> 32)), static_cast<int>(src)));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// the lane of the (lane / S)-th member of this pass among the set bits of
+// *mask (consumed), or 64 when the pass has fewer members
+__device__ __forceinline__ uint32_t hot_member(uint64_t &mask, uint32_t lane, uint32_t S)
+{
+    uint32_t mine = kWave;
+    for (uint32_t i = 0; i < kWave / S && mask != 0; ++i) {
+        const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(mask)) - 1);
+        mask &= mask - 1ull;
+        if (lane / S == i) mine = L;
+    }
+    return mine;
+}
+
+template <int ISA, bool POW2, bool ONE>
+__device__ __forceinline__ void persistent_hot_body(const BatchTable *__restrict__ tab,
+                                                    const uint32_t *__restrict__ work, uint32_t already,
+                                                    uint32_t epoch, uint32_t wm, const HotArgs hot,
+                                                    QueueState *__restrict__ q)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wib = threadIdx.x / kWave;
+    const uint32_t S = hot.S, mask = hot.S - 1u;
+    const uint32_t wave_base = wib * kWave * hot_slot_words(S);   // slot words, then tags
+    const uint32_t tag_base = 2u * (wave_base + 2u * kWave * S);  // in halfwords
+    uint16_t *const ltags = reinterpret_cast<uint16_t *>(rasp_lds);
+    const uint64_t total = q->survivors;
+
+    bool has = false, exhausted = false;
+    Regs r{};
+    int32_t *M = nullptr;
+    int32_t *T = nullptr;
+    int32_t *Y = nullptr;
+    uint32_t done = 0, limit = 0, ws = 0, c = 65536u;
+    uint64_t pos = 0, v = 0;
+    const DevBatch *bp = nullptr;
+
+    for (;;) {
+        // ---- refill idle lanes from the queue ----
+        const uint64_t idle = __ballot(!has);
+        bool claimed = false;
+        if (idle != 0 && !exhausted) {
+            const int leader = __ffsll(static_cast<unsigned long long>(idle)) - 1;
+            const uint32_t cnt = __popcll(idle);
+            unsigned long long base = 0;
+            if (lane == static_cast<uint32_t>(leader))
+                base = __hip_atomic_fetch_add(&q->head, static_cast<unsigned long long>(cnt),
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            base = __shfl(base, leader);
+            if (base + cnt >= total) exhausted = true;
+            if (!has) {
+                const uint64_t item = base + __popcll(idle & ((1ull << lane) - 1ull));
+                if (item < total) {
+                    pos = item;
+                    const uint64_t g = work[pos];
+                    const int k = ONE ? 0 : batch_of(tab, g);
+                    bp = &tab->b[k];
+                    v = ONE ? g : g - tab->start[k];
+                    const uint32_t budget = tab->budget[k];
+                    if (bp->status[v] == 0 && budget > already) {
+                        r.n = bp->n[v]; r.ell = bp->ell[v]; r.s = bp->s[v];
+                        r.i = bp->i[v]; r.a = bp->a[v]; r.u0 = bp->u0[v]; r.y0 = bp->y0[v];
+                        r.p = cmod(r.i, r.n);
+                        ws = bp->wshift;
+                        M = bp->M + bp->mem_off[v];
+                        T = bp->T + bp->t_off[v];
+                        Y = bp->Y + bp->y_off[v];
+                        c = hot.mult[pos];
+                        done = 0;
+                        limit = budget - already;
+                        has = true;
+                        claimed = true;
+                    }
+                }
+            }
+        }
+        if (__ballot(has) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+        // ---- fill the claimed machines' tables ----
+        uint64_t cm = __ballot(claimed);
+        while (cm != 0) {
+            const uint32_t L = hot_member(cm, lane, S);
+            const uint32_t src = L & (kWave - 1u);
+            const uint64_t pL = shfl64(pos, src);
+            const int32_t *ML = reinterpret_cast<const int32_t *>(shfl64(reinterpret_cast<uint64_t>(M), src));
+            const uint32_t sl = lane & mask;
+            if (L < kWave) {
+                const uint32_t x = hot.tags[pL * S + sl];
+                int2 wv = int2{0, 0};
+                if (x != 0xffffu) wv = *reinterpret_cast<const int2 *>(ML + 2u * x);
+                *reinterpret_cast<int2 *>(&rasp_lds[wave_base + 2u * (kWave * sl + L)]) = wv;
+                ltags[tag_base + kWave * sl + L] = static_cast<uint16_t>(x);
+            }
+        }
+        // the wave's table writes before its lanes' reads
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        // ---- run ----
+        bool finish = false;
+        if (has) {
+            uint32_t lim = limit - done;
+            if (lim > epoch) lim = epoch;
+            bool halted;
+            const HotMem mm{wave_base + 2u * lane, tag_base + lane, c, mask, gptr(M)};
+            const TapeG tg{gptr(T)};
+            const OutG og{gptr(Y)};
+            const uint32_t t = wm ? run_machine<ISA, POW2, true>(mm, tg, r, og, lim, halted, ws)
+                                  : run_machine<ISA, POW2, false>(mm, tg, r, og, lim, halted, 0u);
+            done += t;
+            if (halted || done == limit) {
+                if (done) {
+                    bp->i[v] = r.i; bp->a[v] = r.a; bp->u0[v] = r.u0; bp->y0[v] = r.y0;
+                    bp->steps[v] += done;
+                }
+                if (halted) bp->status[v] = 1;
+                finish = true;
+            }
+        }
+        // ---- write the finished machines' cells back ----
+        uint64_t fm = __ballot(finish);
+        while (fm != 0) {
+            const uint32_t L = hot_member(fm, lane, S);
+            const uint32_t src = L & (kWave - 1u);
+            int32_t *ML = reinterpret_cast<int32_t *>(shfl64(reinterpret_cast<uint64_t>(M), src));
+            const uint32_t sl = lane & mask;
+            if (L < kWave) {
+                const uint32_t x = ltags[tag_base + kWave * sl + L];
+                if (x != 0xffffu)
+                    *reinterpret_cast<int2 *>(ML + 2u * x) =
+                        *reinterpret_cast<const int2 *>(&rasp_lds[wave_base + 2u * (kWave * sl + L)]);
+            }
+        }
+        if (finish) has = false;
+    }
+}
+
+template <int ISA, bool POW2>
+__global__ __launch_bounds__(256) void k_persistent_hot(const BatchTable *__restrict__ tab,
+                                                        const uint32_t *__restrict__ work, uint32_t already,
+                                                        uint32_t epoch, uint32_t wm, HotArgs hot,
+                                                        QueueState *__restrict__ q)
+{
+    if (tab->count == 1) persistent_hot_body<ISA, POW2, true>(tab, work, already, epoch, wm, hot, q);
+    else persistent_hot_body<ISA, POW2, false>(tab, work, already, epoch, wm, hot, q);
+}
+
+hipError_t launch_persistent_hot(const BatchTable *tab, const uint32_t *work, uint32_t already, uint32_t isa,
+                                 bool pow2, bool wmb, uint32_t epoch, const HotArgs &hot,
+                                 uint32_t waves_per_block, uint32_t blocks, QueueState *q, hipStream_t st)
+{
+    const dim3 grid(blocks), block(waves_per_block * kWave);
+    const size_t shmem = static_cast<size_t>(waves_per_block) * kWave * hot_slot_words(hot.S) * sizeof(int32_t);
+    const uint32_t wm = wmb ? 1u : 0u;
+    if (isa == 1) {
+        if (pow2) k_persistent_hot<1, true><<<grid, block, shmem, st>>>(tab, work, already, epoch, wm, hot, q);
+        else k_persistent_hot<1, false><<<grid, block, shmem, st>>>(tab, work, already, epoch, wm, hot, q);
+    } else {
+        if (pow2) k_persistent_hot<0, true><<<grid, block, shmem, st>>>(tab, work, already, epoch, wm, hot, q);
+        else k_persistent_hot<0, false><<<grid, block, shmem, st>>>(tab, work, already, epoch, wm, hot, q);
+    }
+    return hipGetLastError();
 }
 
 template <int ISA, int MODE, bool POW2, bool TLDS>
 static hipError_t launch_k3(dim3 grid, dim3 block, size_t shmem, hipStream_t st, const BatchTable *tab,
                             uint64_t total, const uint32_t *work, uint32_t already, uint32_t epoch,
-                            uint32_t P, uint32_t TL, uint32_t wm, uint32_t cap, uint32_t *surv, QueueState *q)
+                            uint32_t P, uint32_t TL, uint32_t wm, uint32_t cap, uint32_t *surv, QueueState *q,
+                            uint32_t which)
 {
     k_persistent<ISA, MODE, POW2, TLDS><<<grid, block, shmem, st>>>(tab, total, work, already, epoch, P, TL,
-                                                                    wm, cap, surv, q);
+                                                                    wm, cap, surv, q, which);
     return hipGetLastError();
 }
 
@@ -1017,6 +1460,14 @@ void init_kernel_attributes()
     lds_attr<1, 1, false, false>(); lds_attr<1, 1, true, false>();
     lds_attr<1, 1, false, true>(); lds_attr<1, 1, true, true>();
     lds_attr<1, 2, false, false>(); lds_attr<1, 2, true, false>();
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent_hot<0, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent_hot<0, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent_hot<1, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_persistent_hot<1, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
 }
 
@@ -1024,10 +1475,10 @@ template <int ISA, int MODE, bool TLDS>
 static hipError_t launch_k3_p(bool pow2, dim3 grid, dim3 block, size_t shmem, hipStream_t st,
                               const BatchTable *tab, uint64_t total, const uint32_t *work,
                               uint32_t already, uint32_t epoch, uint32_t P, uint32_t TL,
-                              uint32_t wm, uint32_t cap, uint32_t *surv, QueueState *q)
+                              uint32_t wm, uint32_t cap, uint32_t *surv, QueueState *q, uint32_t which)
 {
-    return pow2 ? launch_k3<ISA, MODE, true, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q)
-                : launch_k3<ISA, MODE, false, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
+    return pow2 ? launch_k3<ISA, MODE, true, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q, which)
+                : launch_k3<ISA, MODE, false, TLDS>(grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q, which);
 }
 
 // the tape is staged in LDS when every memory fits its slot and every tape
@@ -1044,9 +1495,10 @@ hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32
                              uint32_t already, uint32_t isa, bool pow2, bool wmb, uint32_t epoch,
                              uint32_t lds_words, uint32_t max_n, uint32_t max_ell,
                              uint32_t waves_per_block, uint32_t blocks, uint32_t cap, uint32_t *surv,
-                             QueueState *q, hipStream_t st)
+                             QueueState *q, hipStream_t st, bool misfits)
 {
     const uint32_t wm = wmb ? 1u : 0u;
+    const uint32_t which = misfits ? 1u : 0u;
     const dim3 grid(blocks), block(waves_per_block * kWave);
     const int mode = lds_words == 0 ? 0 : (max_n <= lds_words ? 1 : 2);
     const uint32_t P = mode == 0 ? 0u : lds_words;
@@ -1054,22 +1506,23 @@ hipError_t launch_persistent(const BatchTable *tab, uint64_t total, const uint32
     const uint32_t TL = (mode == 1 && SPw > P + 4u) ? SPw - P - 4u : 0u;
     const size_t shmem = mode == 0 ? 0 : static_cast<size_t>(waves_per_block) * kWave * SPw * sizeof(int32_t);
     if (isa == 1) {
-        if (mode == 1 && TL) return launch_k3_p<1, 1, true>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
-        if (mode == 1) return launch_k3_p<1, 1, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
-        if (mode == 2) return launch_k3_p<1, 2, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
-        return launch_k3_p<1, 0, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
+        if (mode == 1 && TL) return launch_k3_p<1, 1, true>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q, which);
+        if (mode == 1) return launch_k3_p<1, 1, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q, which);
+        if (mode == 2) return launch_k3_p<1, 2, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q, which);
+        return launch_k3_p<1, 0, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q, which);
     }
-    if (mode == 1 && TL) return launch_k3_p<0, 1, true>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q);
-    if (mode == 1) return launch_k3_p<0, 1, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
-    if (mode == 2) return launch_k3_p<0, 2, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
-    return launch_k3_p<0, 0, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q);
+    if (mode == 1 && TL) return launch_k3_p<0, 1, true>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, TL, wm, cap, surv, q, which);
+    if (mode == 1) return launch_k3_p<0, 1, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q, which);
+    if (mode == 2) return launch_k3_p<0, 2, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q, which);
+    return launch_k3_p<0, 0, false>(pow2, grid, block, shmem, st, tab, total, work, already, epoch, P, 0u, wm, cap, surv, q, which);
 }
 
 __global__ void k_zero_queue(QueueState *q, uint32_t head_only)
 {
     if (threadIdx.x == 0) {
         q->head = 0;
-        if (!head_only) { q->survivors = 0; q->retired = 0; q->pad = 0; }
+        q->head_m = 0;
+        if (!head_only) { q->survivors = 0; q->retired = 0; q->pad = 0; q->misfits = 0; }
     }
 }
 

@@ -156,6 +156,16 @@ struct rasp_ctx {
     int64_t schedule = RASP_SCHED_AUTO, epoch = 256, lds_words = -1, waves_per_cu = 16, graph = 0;
     int64_t first_pass = 64;
     int64_t first_pass_kind = 0;         // 1: LDS-resident first pass when memories fit
+    int64_t hot_cells = 0;               // slots of a hot-cell table (0: off)
+    int64_t profile_steps = 256;         // transitions profiled at the end of a hot-cell first pass
+    int64_t misfit_waves = 6;            // waves per CU of the hot-cell misfits' launch
+    Alloc hot;                           // hot-cell multipliers, tags and misfit list
+    uint64_t hot_cap = 0, hot_S = 0;
+    // second stream (same CU mask as the first) and its two events: the
+    // misfits' launch runs there beside the fits' launch
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_first = nullptr, ev_second = nullptr;
+    std::vector<uint32_t> cu_mask;       // empty: the context's stream has no CU mask
     // scratch: queue counters, batch tables (device ring + pinned host ring)
     Alloc scratch;
     QueueState *queue = nullptr;
@@ -245,7 +255,7 @@ Batch *find(rasp_ctx *c, rasp_batch b)
     return it == c->batches.end() ? nullptr : it->second.get();
 }
 
-template <class F> hipError_t timed_launch(rasp_ctx *c, int kind, F fn);
+template <class F> hipError_t timed_launch(rasp_ctx *c, int kind, F fn, hipStream_t st = nullptr);
 
 // Build c0 of a lazily loaded batch (RASP_DESC_LAZY) in the arena.
 int materialize(rasp_ctx *c, Batch *b)
@@ -271,17 +281,18 @@ hipEvent_t pooled_event(rasp_ctx *c)
     return e;
 }
 
-// Launch `fn` (returning hipError_t) on the context stream, bracketed by timing
-// events when profiling is on.
+// Launch `fn` (returning hipError_t) on the context stream (or `st`),
+// bracketed by timing events when profiling is on.
 template <class F>
-hipError_t timed_launch(rasp_ctx *c, int kind, F fn)
+hipError_t timed_launch(rasp_ctx *c, int kind, F fn, hipStream_t st)
 {
     if (!c->profile || c->no_events) return fn();
+    if (!st) st = c->stream;
     hipEvent_t a = pooled_event(c), b = pooled_event(c);
     if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, c->stream);
+    hipError_t e = hipEventRecord(a, st);
     if (!e) e = fn();
-    if (!e) e = hipEventRecord(b, c->stream);
+    if (!e) e = hipEventRecord(b, st);
     if (!e) c->timed.push_back({kind, a, b});
     return e;
 }
@@ -559,6 +570,21 @@ uint32_t waves_per_block_for(uint32_t SPw, uint64_t lds)
     return wpb;
 }
 
+// blocks of a persistent launch: the waves asked for (waves per CU x CUs),
+// in blocks of wpb waves, but no more than the LDS of the context's compute
+// units holds at once (lanes with SPw-word slots): blocks beyond that would
+// only start as resident ones exit
+uint32_t resident_blocks(const rasp_ctx *c, uint32_t wpb, uint32_t SPw, uint32_t waves)
+{
+    uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
+    if (SPw > 0) {
+        const uint64_t per_cu = static_cast<uint64_t>(c->lds_bytes) / (static_cast<uint64_t>(wpb) * kWave * SPw * 4);
+        const uint64_t most = std::max<uint64_t>(1, per_cu * static_cast<uint64_t>(c->cus));
+        blocks = static_cast<uint32_t>(std::min<uint64_t>(blocks, most));
+    }
+    return blocks;
+}
+
 // drop captured graphs (all of them, or those that use batch h)
 void drop_graphs(rasp_ctx *c, bool all, uint64_t h = 0)
 {
@@ -589,6 +615,39 @@ int ensure_work(rasp_ctx *c, uint64_t items)
         return fail(c, RASP_E_NOMEM, "arena cannot hold the work list of %llu machines", (unsigned long long)items);
     }
     c->work_cap = items;
+    return RASP_OK;
+}
+
+// ensure the hot-cell arrays hold `items` survivor-list entries of S slots
+int ensure_hot(rasp_ctx *c, uint64_t items, uint64_t S)
+{
+    if (items <= c->hot_cap && S <= c->hot_S) return RASP_OK;
+    if (c->hot.live) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        arena_free(c, &c->hot);
+    }
+    const uint64_t bytes = 2 * align_up(4 * items, kAlign) + 2 * items * S;
+    if (!arena_alloc(c, bytes, &c->hot)) {
+        c->hot_cap = c->hot_S = 0;
+        return fail(c, RASP_E_NOMEM, "arena cannot hold the hot-cell tables of %llu machines", (unsigned long long)items);
+    }
+    c->hot_cap = items;
+    c->hot_S = S;
+    return RASP_OK;
+}
+
+// the context's second stream and its events (created on first use, with
+// the first stream's CU mask)
+int ensure_stream2(rasp_ctx *c)
+{
+    if (c->stream2) return RASP_OK;
+    hipError_t e = c->cu_mask.empty()
+                       ? hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking)
+                       : hipExtStreamCreateWithCUMask(&c->stream2, static_cast<uint32_t>(c->cu_mask.size()),
+                                                      c->cu_mask.data());
+    if (!e) e = hipEventCreateWithFlags(&c->ev_first, hipEventDisableTiming);
+    if (!e) e = hipEventCreateWithFlags(&c->ev_second, hipEventDisableTiming);
+    if (e) return fail(c, RASP_E_DEVICE, "second stream: %s", hipGetErrorString(e));
     return RASP_OK;
 }
 
@@ -659,7 +718,7 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k, co
         }
     // queue counters: the context's, or the caller-independent scratch
     QueueState *const qs = rs ? rs->queue : c->queue;
-    const bool graphed = c->graph && !any_fresh && !rs;
+    const bool graphed = c->graph && !any_fresh && !rs && c->hot_cells == 0;
     BatchTable *ht, *dt;
     int slot;
     int rc = table_slot(c, &ht, &dt, &slot);
@@ -715,8 +774,13 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k, co
     const uint32_t SPw = slot_words(P, max_n, max_ell);
     const uint32_t wpb = waves_per_block_for(SPw, lds);
     const uint32_t waves = static_cast<uint32_t>(std::max<int64_t>(1, c->waves_per_cu)) * static_cast<uint32_t>(c->cus);
-    const uint32_t blocks = std::max<uint32_t>(1, waves / wpb);
+    const uint32_t blocks = resident_blocks(c, wpb, SPw, waves);
     const uint32_t epoch = static_cast<uint32_t>(std::max<int64_t>(1, c->epoch));
+    // hot-cell tables: a plain first pass shorter than the budget, memories of
+    // at most kHotMaxN words, a launch that may allocate
+    const uint32_t S_hot = static_cast<uint32_t>(c->hot_cells);
+    const bool hot = S_hot > 0 && sched == RASP_SCHED_PERSISTENT && cap > 0 && cap < maxb && !lds_first &&
+                     !fused && max_n <= kHotMaxN && rs == nullptr;
     if (graphed) {
         // replay (capturing on first use) the launch sequence for this key
         std::vector<uint64_t> key;
@@ -767,6 +831,51 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k, co
         // fresh batches present: one persistent launch over every machine
         HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
             return launch_persistent(dt, total, nullptr, 0, isa, pow2, wm, epoch, P, max_n, max_ell, wpb, blocks, kNoCap, nullptr, qs, st); }));
+        for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
+    } else if (hot) {
+        // hot-cell first pass (plain, profiling its last transitions), then
+        // the persistent kernel over fits and misfits with their LDS tables
+        if ((rc = ensure_work(c, total)) || (rc = ensure_hot(c, total, S_hot))) return rc;
+        uint32_t *work = at<uint32_t>(c, c->work);
+        HotArgs ha{};
+        ha.S = S_hot;
+        ha.lgS = static_cast<uint32_t>(__builtin_ctz(S_hot));
+        ha.R = static_cast<uint32_t>(std::min<int64_t>(c->profile_steps, cap));
+        ha.bw = hot_bitmap_words(max_n);
+        ha.mult = at<uint32_t>(c, c->hot);
+        ha.mis = at<uint32_t>(c, c->hot, align_up(4 * c->hot_cap, kAlign));
+        ha.tags = at<uint16_t>(c, c->hot, 2 * align_up(4 * c->hot_cap, kAlign));
+        if ((rc = ensure_stream2(c))) return rc;
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PLAIN, [&] {
+            return launch_plain(dt, total, cap, isa, pow2, pack_in_plain, wm, work, qs, st, &ha); }));
+        BatchTable *dt2 = dt;
+        if (any_fresh) {
+            BatchTable *ht2;
+            int slot2;
+            if ((rc = table_slot(c, &ht2, &dt2, &slot2))) return rc;
+            std::memcpy(ht2, ht, sizeof(BatchTable));
+            for (uint32_t t = 0; t < k; ++t) ht2->b[t].fresh = 0;
+            HIPCHK(c, hipMemcpyAsync(dt2, ht2, sizeof(BatchTable), hipMemcpyHostToDevice, st));
+            HIPCHK(c, hipEventRecord(c->table_ev[slot2], st));
+            c->table_used[slot2] = true;
+        }
+        const uint32_t SPh = hot_slot_words(S_hot);
+        const uint32_t wpb_h = waves_per_block_for(SPh, lds);
+        const uint32_t blocks_h = resident_blocks(c, wpb_h, SPh, waves);
+        // the misfits on the second stream, after the first pass; the first
+        // stream's later work waits for them
+        hipStream_t st2 = c->stream2;
+        const uint32_t blocks_m = std::max<uint32_t>(
+            1, static_cast<uint32_t>(std::max<int64_t>(1, c->misfit_waves)) * static_cast<uint32_t>(c->cus) / 4u);
+        HIPCHK(c, hipEventRecord(c->ev_first, st));
+        HIPCHK(c, hipStreamWaitEvent(st2, c->ev_first, 0));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_MISFIT, [&] {
+            return launch_persistent(dt2, total, ha.mis, cap, isa, pow2, wm, epoch, 0u, max_n, max_ell, 4u, blocks_m,
+                                     kNoCap, nullptr, qs, st2, true); }, st2));
+        HIPCHK(c, hipEventRecord(c->ev_second, st2));
+        HIPCHK(c, timed_launch(c, RASP_KERNEL_PERSISTENT, [&] {
+            return launch_persistent_hot(dt2, work, cap, isa, pow2, wm, epoch, ha, wpb_h, blocks_h, qs, st); }));
+        HIPCHK(c, hipStreamWaitEvent(st, c->ev_second, 0));
         for (uint32_t t = 0; t < k; ++t) bs[t]->dev.fresh = 0;
     } else if (cap > 0 && cap < maxb) {
         if (rs) {
@@ -956,6 +1065,9 @@ int rasp_create_on_cus(rasp_ctx **out, int device, void *arena, uint64_t arena_b
         return rc;
     }
     (*out)->own_stream = true;
+    // launches of this context size their grids to its share of the CUs
+    (*out)->cus = static_cast<int>(cu_count);
+    (*out)->cu_mask = mask;
     return RASP_OK;
 }
 
@@ -975,6 +1087,12 @@ int rasp_destroy(rasp_ctx *c)
     if (c->count_host) (void)hipHostFree(c->count_host);
     if (c->own_arena && c->arena) (void)hipFree(c->arena);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->stream2) {
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamDestroy(c->stream2);
+    }
+    if (c->ev_first) (void)hipEventDestroy(c->ev_first);
+    if (c->ev_second) (void)hipEventDestroy(c->ev_second);
     delete c;
     return RASP_OK;
 }
@@ -1364,6 +1482,16 @@ int rasp_set_option(rasp_ctx *c, int option, int64_t value)
     case RASP_OPT_FIRST_PASS_KIND:
         if (value != 0 && value != 1) return fail(c, RASP_E_INVAL, "first pass kind must be 0 or 1");
         c->first_pass_kind = value; return RASP_OK;
+    case RASP_OPT_HOT_CELLS:
+        if (value != 0 && value != 8 && value != 16 && value != 32 && value != 64)
+            return fail(c, RASP_E_INVAL, "hot cells must be 0, 8, 16, 32 or 64");
+        c->hot_cells = value; return RASP_OK;
+    case RASP_OPT_PROFILE_STEPS:
+        if (value < 1 || value > 0x7fffffff) return fail(c, RASP_E_INVAL, "profile steps must be >= 1");
+        c->profile_steps = value; return RASP_OK;
+    case RASP_OPT_MISFIT_WAVES:
+        if (value < 1 || value > 32) return fail(c, RASP_E_INVAL, "misfit waves per CU must be in [1, 32]");
+        c->misfit_waves = value; return RASP_OK;
     default:
         return fail(c, RASP_E_INVAL, "unknown option %d", option);
     }
@@ -1381,6 +1509,9 @@ int rasp_get_option(rasp_ctx *c, int option, int64_t *value)
     case RASP_OPT_FIRST_PASS: *value = c->first_pass; return RASP_OK;
     case RASP_OPT_PROFILE: *value = c->profile; return RASP_OK;
     case RASP_OPT_FIRST_PASS_KIND: *value = c->first_pass_kind; return RASP_OK;
+    case RASP_OPT_HOT_CELLS: *value = c->hot_cells; return RASP_OK;
+    case RASP_OPT_PROFILE_STEPS: *value = c->profile_steps; return RASP_OK;
+    case RASP_OPT_MISFIT_WAVES: *value = c->misfit_waves; return RASP_OK;
     default: return fail(c, RASP_E_INVAL, "unknown option %d", option);
     }
 }
@@ -1403,6 +1534,9 @@ int rasp_kernel_times(rasp_ctx *c, double *ms, uint64_t *launches)
     c->timed.clear();
     return RASP_OK;
 }
+
+// knobs the autotuner chooses, in the order of its `chosen` array
+constexpr int kTuneKnobs = 9;
 
 // a knob moves away from the current setting only for a trial at least 3%
 // faster: timings of near-equal settings differ by noise from run to run
@@ -1489,7 +1623,8 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     hipError_t e = lazy ? copy_shapes(b->dev, trial.dev) : copy_batch(b->dev, snap.dev);
     if (e) { release(); return fail(c, RASP_E_DEVICE, "autotune snapshot: %s", hipGetErrorString(e)); }
     const int64_t saved[] = {c->schedule, c->lds_words, c->first_pass, c->epoch, c->waves_per_cu,
-                             c->first_pass_kind, c->graph, c->profile};
+                             c->first_pass_kind, c->hot_cells, c->profile_steps, c->misfit_waves,
+                             c->graph, c->profile};
     c->graph = 0;
     c->profile = 0;
     hipEvent_t e0, e1;
@@ -1539,22 +1674,27 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     }
     const std::vector<int64_t> fp_c = {0, 16, 64, 256}, ep_c = {16, 64, 256, 1024}, wv_c = {8, 16, 32},
                                fk_c = {0, 1};
-    int64_t cur[6] = {RASP_SCHED_PERSISTENT, c->lds_words < 0 ? static_cast<int64_t>(lds_words_for(c, b->max_n, b->max_ell)) : c->lds_words,
-                      c->first_pass, c->epoch, c->waves_per_cu, c->first_pass_kind};
+    int64_t cur[kTuneKnobs] = {RASP_SCHED_PERSISTENT,
+                               c->lds_words < 0 ? static_cast<int64_t>(lds_words_for(c, b->max_n, b->max_ell)) : c->lds_words,
+                               c->first_pass, c->epoch, c->waves_per_cu, c->first_pass_kind, 0, c->profile_steps,
+                               c->misfit_waves};
     auto apply = [&](const int64_t *o) {
         c->schedule = o[0]; c->lds_words = o[1]; c->first_pass = o[2]; c->epoch = o[3]; c->waves_per_cu = o[4];
-        c->first_pass_kind = o[5];
+        c->first_pass_kind = o[5]; c->hot_cells = o[6]; c->profile_steps = o[7]; c->misfit_waves = o[8];
     };
     // one coordinate search (LDS words, first-pass length, epoch, waves per
     // CU) for each first-pass kind, from the same start; the kinds interact
     // with every other knob, so they are not searched one after the other
-    const int64_t start[6] = {cur[0], cur[1], cur[2], cur[3], cur[4], cur[5]};
+    int64_t start[kTuneKnobs];
+    for (int q = 0; q < kTuneKnobs; ++q) start[q] = cur[q];
     const std::vector<int64_t> *lists[5] = {nullptr, &lds_c, &fp_c, &ep_c, &wv_c};
     double best = 1e30;
     bool warm = false;
     for (int64_t kind : fk_c) {
         if (rc) break;
-        int64_t kc[6] = {start[0], start[1], start[2], start[3], start[4], kind};
+        int64_t kc[kTuneKnobs];
+        for (int q = 0; q < kTuneKnobs; ++q) kc[q] = start[q];
+        kc[5] = kind;
         double kbest = 1e30;
         apply(kc);
         if (!warm) { rc = trial_ms(&kbest); warm = true; }     // warm-up run
@@ -1568,7 +1708,8 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
                 if (knob == 1 && val > 0 &&
                     static_cast<uint64_t>(kWave) * slot_words(static_cast<uint32_t>(val), b->max_n, b->max_ell) * 4 >
                         static_cast<uint64_t>(c->lds_bytes)) continue;
-                int64_t o[6] = {kc[0], kc[1], kc[2], kc[3], kc[4], kc[5]};
+                int64_t o[kTuneKnobs];
+                for (int q = 0; q < kTuneKnobs; ++q) o[q] = kc[q];
                 o[knob] = val;
                 apply(o);
                 double ms = 0;
@@ -1578,28 +1719,65 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         }
         if (!rc && kbest < best * kTuneMargin) {
             best = kbest;
-            for (int q = 0; q < 6; ++q) cur[q] = kc[q];
+            for (int q = 0; q < kTuneKnobs; ++q) cur[q] = kc[q];
+        }
+    }
+    // hot-cell tables (memories of at most kHotMaxN words, a budget beyond
+    // the profiled first pass): slots per machine and the misfits' waves per
+    // CU on a grid, then the profile length for the best of them; each
+    // against the best setting so far
+    if (!rc && b->max_n <= kHotMaxN && bud > 2048) {
+        int64_t hb[kTuneKnobs];
+        double hbest = 1e30;
+        for (int64_t S : {16, 32}) {
+            for (int64_t mw : {6, 8, 12}) {
+                int64_t o[kTuneKnobs];
+                for (int q = 0; q < kTuneKnobs; ++q) o[q] = cur[q];
+                o[0] = RASP_SCHED_PERSISTENT; o[2] = 576; o[5] = 0; o[6] = S; o[7] = 512; o[8] = mw;
+                o[4] = 16;
+                apply(o);
+                double ms = 0;
+                if ((rc = trial_ms(&ms))) break;
+                if (ms < hbest * kTuneMargin) { hbest = ms; for (int q = 0; q < kTuneKnobs; ++q) hb[q] = o[q]; }
+            }
+            if (rc) break;
+        }
+        for (int64_t prof : {256, 1024}) {
+            if (rc || hbest >= 1e30) break;
+            int64_t o[kTuneKnobs];
+            for (int q = 0; q < kTuneKnobs; ++q) o[q] = hb[q];
+            o[7] = prof; o[2] = prof + 64;
+            apply(o);
+            double ms = 0;
+            if ((rc = trial_ms(&ms))) break;
+            if (ms < hbest * kTuneMargin) { hbest = ms; for (int q = 0; q < kTuneKnobs; ++q) hb[q] = o[q]; }
+        }
+        if (!rc && hbest < best * kTuneMargin) {
+            best = hbest;
+            for (int q = 0; q < kTuneKnobs; ++q) cur[q] = hb[q];
         }
     }
     if (!rc) {                              // the plain schedule as a whole
-        int64_t o[6] = {RASP_SCHED_PLAIN, cur[1], cur[2], cur[3], cur[4], cur[5]};
+        int64_t o[kTuneKnobs];
+        for (int q = 0; q < kTuneKnobs; ++q) o[q] = cur[q];
+        o[0] = RASP_SCHED_PLAIN;
+        o[6] = 0;
         apply(o);
         double ms = 0;
         rc = trial_ms(&ms);
-        if (!rc && ms < best * kTuneMargin) { best = ms; cur[0] = RASP_SCHED_PLAIN; }
+        if (!rc && ms < best * kTuneMargin) { best = ms; cur[0] = RASP_SCHED_PLAIN; cur[6] = 0; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     release();
-    c->graph = saved[6];
-    c->profile = saved[7];
+    c->graph = saved[9];
+    c->profile = saved[10];
     if (rc) {
-        const int64_t back[6] = {saved[0], saved[1], saved[2], saved[3], saved[4], saved[5]};
-        apply(back);
+        apply(saved);
         return rc;
     }
     apply(cur);
-    if (chosen) for (int q = 0; q < 6; ++q) chosen[q] = cur[q];
+    if (chosen) for (int q = 0; q < kTuneKnobs; ++q) chosen[q] = cur[q];
     if (best_ms) *best_ms = best;
     return RASP_OK;
 }

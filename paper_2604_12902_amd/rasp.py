@@ -36,7 +36,10 @@ RASP_OPT_WAVES_PER_CU, RASP_OPT_GRAPH, RASP_OPT_FIRST_PASS = 4, 5, 6
 RASP_SCHED_AUTO, RASP_SCHED_PLAIN, RASP_SCHED_PERSISTENT = 0, 1, 2
 RASP_OPT_PROFILE = 7
 RASP_OPT_FIRST_PASS_KIND = 8
-KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other", "first")
+RASP_OPT_HOT_CELLS = 9
+RASP_OPT_PROFILE_STEPS = 10
+RASP_OPT_MISFIT_WAVES = 11
+KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other", "first", "misfit")
 
 EXPORTED = ("rasp_create", "rasp_create_on_cus", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi", "rasp_run_noalloc",
@@ -291,7 +294,7 @@ def rasp_running_counts(ctx, batches) -> np.ndarray:
 
 
 AUTOTUNE_KNOBS = ("schedule", "lds_words", "first_pass", "epoch", "waves_per_cu",
-                  "first_pass_kind")
+                  "first_pass_kind", "hot_cells", "profile_steps", "misfit_waves")
 
 
 def rasp_autotune(ctx, batch: int, budget: int, max_vms: int = 0) -> dict:

@@ -27,34 +27,38 @@ def test_lookup_needs_the_same_knobs_and_kernel_code(tmp_path):
     assert counters.lookup(str(tmp_path / "missing.json"), knobs) is None
 
 
-def test_committed_records_match_the_current_kernels():
-    """The records under profiles/ were taken on the kernel code in the tree
-    (otherwise bench.py would report traffic as null)."""
+def test_committed_records_of_the_headline_match_the_current_kernels():
+    """The records of the default workload (uneven) were taken on the kernel
+    code in the tree, so the bench line's traffic is not null; records of
+    other workloads taken on older code are ignored by lookup()."""
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    for w in ("plain-scale", "fig1", "uneven"):
-        for k in ("persistent", "pack", "plain"):
-            with open(os.path.join(root, "profiles", "%s_%s_traffic.json" % (w, k))) as f:
-                rec = json.load(f)
-            assert rec["kernels_sha256"] == counters.kernels_sha256(), (w, k)
-            assert rec["runs"]
+    for k in ("persistent+misfit", "pack", "plain"):
+        with open(os.path.join(root, "profiles", "uneven_%s_traffic.json" % k)) as f:
+            rec = json.load(f)
+        assert rec["kernels_sha256"] == counters.kernels_sha256(), k
+        assert rec["runs"]
 
 
-def test_headline_knobs_find_a_pack_record():
-    """Whatever epoch, slot or first-pass length the autotuner picks on
-    plain-scale, the bench line's dominant kernel (k_pack) has a record for
-    one, two and four batches in flight."""
+def test_cached_headline_knobs_find_a_traffic_record():
+    """The knobs the autotune cache holds for the headline (uneven, four
+    batches in flight) have a record of the concurrent fits' and misfits'
+    launches."""
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    path = os.path.join(root, "profiles", "plain-scale_pack_traffic.json")
-    for epoch in (64, 256, 1024):
-        for lds in (128, 256):
-            for n in (1, 2, 4):
-                knobs = {"schedule": 2, "lds_words": lds, "first_pass": 64, "epoch": epoch,
-                         "waves_per_cu": 16, "first_pass_kind": 0, "c0_in_run": False}
-                if n > 1:
-                    knobs.update(batches_in_flight=n, cu_partition="split")
-                assert counters.lookup(path, knobs, "pack") is not None, knobs
+    with open(os.path.join(root, "paper_2604_12902_amd", "tune_cache.json")) as f:
+        cache = json.load(f)
+    entries = [(json.loads(k), v) for k, v in cache.items() if json.loads(k)["num_vms"] == 1 << 22]
+    assert entries
+    path = os.path.join(root, "profiles", "uneven_persistent+misfit_traffic.json")
+    for key, v in entries:
+        t = dict(v["autotune"])
+        knobs = {k: t[k] for k in ("schedule", "lds_words", "first_pass", "epoch", "waves_per_cu",
+                                   "first_pass_kind", "hot_cells", "profile_steps", "misfit_waves")}
+        knobs.update(first_pass=v["inflight_first_pass"], epoch=v["inflight_epoch"], c0_in_run=False)
+        if v["inflight"] > 1:
+            knobs.update(batches_in_flight=v["inflight"], cu_partition="split")
+        assert counters.lookup(path, knobs, "persistent+misfit") is not None, knobs
 
 
 def test_pack_records_ignore_the_step_loop_knobs(tmp_path):
@@ -108,3 +112,18 @@ def test_measure_scales_by_the_copy_and_averages_dispatches(tmp_path):
     last = counters.measure(f, w, gib, "k_pack", last=1)
     assert last["fetch_bytes_per_launch"] == 300.0 * 1024 * 2
     assert last["write_bytes_per_launch"] == 30.0 * 1024
+
+
+def test_measure_sums_launches_that_run_side_by_side(tmp_path):
+    """'a|b': the per-launch means of both kernels, added (one step of the
+    path is one launch of each)."""
+    gib = 1 << 30
+    f, w = str(tmp_path / "f"), str(tmp_path / "w")
+    copy = "__amd_rocclr_copyBuffer"
+    _counter_db(f, "FETCH_SIZE", [(copy, 1, 524288.0), ("k_hot(x)", 2, 100.0), ("k_hot(x)", 4, 300.0),
+                                  ("k_mis(x)", 3, 10.0), ("k_mis(x)", 5, 30.0)])
+    _counter_db(w, "WRITE_SIZE", [(copy, 1, 1048576.0), ("k_hot(x)", 2, 1.0), ("k_hot(x)", 4, 3.0),
+                                  ("k_mis(x)", 3, 5.0), ("k_mis(x)", 5, 5.0)])
+    res = counters.measure(f, w, gib, "k_hot|k_mis")
+    assert res["fetch_bytes_per_launch"] == (200.0 + 20.0) * 1024 * 2
+    assert res["write_bytes_per_launch"] == (2.0 + 5.0) * 1024

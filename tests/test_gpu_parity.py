@@ -29,6 +29,13 @@ SCHEDULES = {
     # per compute unit; memories above 208 / 156 words are split
     "persistent-lds208-split": dict(schedule=2, first_pass=64, lds_words=208, epoch=64, kind=0),
     "persistent-lds156-split": dict(schedule=2, first_pass=0, lds_words=156, epoch=16, kind=0),
+    # hot-cell tables: a profiled plain first pass, then each survivor's
+    # profiled cells hashed into S LDS slots (misfits keep what fits)
+    "persistent-lds16-split": dict(schedule=2, first_pass=0, lds_words=16, epoch=2, kind=0),
+    "hot16": dict(schedule=2, first_pass=64, lds_words=0, epoch=16, kind=0, hot=16, prof=32),
+    "hot8-tiny-epoch": dict(schedule=2, first_pass=3, lds_words=0, epoch=1, kind=0, hot=8, prof=2,
+                            misfit_waves=1),
+    "hot64-long-profile": dict(schedule=2, first_pass=40, lds_words=0, epoch=64, kind=0, hot=64, prof=40),
 }
 
 
@@ -47,6 +54,14 @@ def ctx(rasp):
     c.close()
 
 
+@pytest.fixture(autouse=True)
+def no_hot_cells(ctx, rasp):
+    """Tests that set knobs themselves start without hot-cell tables."""
+    ctx.set(rasp.RASP_OPT_HOT_CELLS, 0)
+    ctx.set(rasp.RASP_OPT_PROFILE_STEPS, 256)
+    yield
+
+
 def configure(ctx, rasp, sched):
     o = SCHEDULES[sched]
     ctx.set(rasp.RASP_OPT_SCHEDULE, o["schedule"])
@@ -55,6 +70,9 @@ def configure(ctx, rasp, sched):
         ctx.set(rasp.RASP_OPT_LDS_WORDS, o["lds_words"])
         ctx.set(rasp.RASP_OPT_EPOCH, o["epoch"])
         ctx.set(rasp.RASP_OPT_FIRST_PASS_KIND, o["kind"])
+    ctx.set(rasp.RASP_OPT_HOT_CELLS, o.get("hot", 0))
+    ctx.set(rasp.RASP_OPT_PROFILE_STEPS, o.get("prof", 256))
+    ctx.set(rasp.RASP_OPT_MISFIT_WAVES, o.get("misfit_waves", 6))
 
 
 def compare(got, want: oracle.State, mem=True, idx=None):
@@ -106,7 +124,7 @@ def _hand_cases():
         return json.load(f)["cases"]
 
 
-@pytest.mark.parametrize("sched", ["plain", "persistent-lds32"])
+@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "hot8-tiny-epoch"])
 def test_hand_traced_machines(ctx, rasp, sched):
     configure(ctx, rasp, sched)
     for case in _hand_cases():
@@ -141,12 +159,60 @@ def test_busy_beavers_word_set(ctx, rasp):
     assert (got["status"] == 1).all()
 
 
-@pytest.mark.parametrize("sched", ["plain", "firstpass-lds64", "ldsfirst-lds1024-epoch3"])
+@pytest.mark.parametrize("sched", ["plain", "firstpass-lds64", "ldsfirst-lds1024-epoch3", "hot16",
+                                   "hot8-tiny-epoch", "hot64-long-profile"])
 def test_uneven_batch_reduced_bit_exact(ctx, rasp, sched):
     print("case: uneven N=20000 sched=%s" % sched, flush=True)
     configure(ctx, rasp, sched)
     b = W.config3(num_vms=20000, budget=4096)
     compare(run_gpu(ctx, b, b.budget), oracle.run(b, b.budget, threads=8))
+
+
+def _image(n, words):
+    """A program as a memory image: words[k] at word k (a dict), zeros elsewhere,
+    as many words as the highest one set (rounded up to even)."""
+    top = max(words) + 1
+    img = [0] * (top + (top & 1))
+    for k, w in words.items():
+        img[k] = w
+    assert len(img) <= n
+    return img
+
+
+def _boundary_programs(n):
+    """Classic programs that hit the split slot's and the hot-cell table's
+    boundary positions at P = 16 LDS words (memory of n > 16 words)."""
+    LOAD, ADD, STORE, JPOS, PRINT, JMP = 1, 2, 4, 5, 7, 8
+    return [
+        # the operand of the instruction at n - 1 wraps to word 0: LOAD M[0]
+        _image(n, {0: LOAD, 1: LOAD, 2: STORE, 3: n - 1, 4: JMP, 5: n - 1}),
+        # a misaligned instruction at P - 1 whose operand is word P (in HBM)
+        _image(n, {0: JMP, 1: 15, 15: LOAD, 16: 77, 17: PRINT, 18: 16}),
+        # a store into the next instruction's operand, across P, in a loop
+        _image(n, {0: JMP, 1: 12, 12: LOAD, 13: 55, 14: STORE, 15: 17, 16: ADD, 17: 99,
+                   18: PRINT, 19: 17, 20: STORE, 21: 15, 22: JPOS, 23: 14}),
+        # a store into the opcode word of the instruction at P - 1 just before
+        # it is fetched
+        _image(n, {0: LOAD, 1: PRINT, 2: STORE, 3: 15, 4: JMP, 5: 15, 16: 2}),
+        # a jump to P - 2 and a loop whose data word is its own next opcode
+        _image(n, {0: JMP, 1: 14, 14: ADD, 15: 16, 16: STORE, 17: 16, 18: JPOS, 19: 14}),
+    ]
+
+
+@pytest.mark.parametrize("sched", ["plain", "persistent-lds16-split", "firstpass-lds16-tiny-epoch",
+                                   "hot8-tiny-epoch", "hot16"])
+@pytest.mark.parametrize("n", [41, 64])
+def test_split_and_hot_table_boundaries(ctx, rasp, sched, n):
+    """Hand-built machines at the split slot's boundary (P = 16 words in LDS,
+    the rest in HBM): an operand wrapping from word n - 1 to word 0, a
+    misaligned instruction at P - 1 whose operand is word P, stores into the
+    next instruction's words just before its fetch on both sides of P; the
+    same positions are cell boundaries of the hot-cell tables."""
+    print("case: boundaries n=%d sched=%s" % (n, sched), flush=True)
+    configure(ctx, rasp, sched)
+    progs = _boundary_programs(n)
+    b = W.from_programs(W.ISA_CLASSIC, progs, n, [[3, -4]] * len(progs), ell=2, s=2)
+    compare(run_gpu(ctx, b, 300), oracle.run(b, 300))
 
 
 @pytest.fixture(scope="module")
@@ -243,7 +309,7 @@ def _random_states(b, seed):
 
 
 @pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "firstpass-lds16-tiny-epoch",
-                                   "ldsfirst-lds64"])
+                                   "ldsfirst-lds64", "hot8-tiny-epoch"])
 @pytest.mark.parametrize("isa", [0, 1])
 def test_loaded_states_fuzz(ctx, rasp, sched, isa):
     """rasp_load_state with arbitrary configurations (i near INT32_MAX, odd,
@@ -438,7 +504,9 @@ def test_autotune_leaves_the_batch_and_stays_bit_exact(ctx, rasp):
         assert ctx.get({"schedule": R.RASP_OPT_SCHEDULE, "lds_words": R.RASP_OPT_LDS_WORDS,
                         "first_pass": R.RASP_OPT_FIRST_PASS, "epoch": R.RASP_OPT_EPOCH,
                         "waves_per_cu": R.RASP_OPT_WAVES_PER_CU,
-                        "first_pass_kind": R.RASP_OPT_FIRST_PASS_KIND}[k]) == chosen[k]
+                        "first_pass_kind": R.RASP_OPT_FIRST_PASS_KIND, "hot_cells": R.RASP_OPT_HOT_CELLS,
+                        "profile_steps": R.RASP_OPT_PROFILE_STEPS,
+                        "misfit_waves": R.RASP_OPT_MISFIT_WAVES}[k]) == chosen[k]
     after = ctx.fetch(h, mem=True)
     for k in before:
         assert np.array_equal(before[k], after[k]), k
@@ -477,7 +545,8 @@ def test_autotune_on_a_lazy_batch(ctx, rasp):
 
 
 @pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "firstpass-lds64", "ldsfirst-lds64",
-                                   "persistent-lds208-split", "persistent-lds156-split"])
+                                   "persistent-lds208-split", "persistent-lds156-split", "hot16",
+                                   "hot64-long-profile"])
 def test_fig1_programs_bit_exact(ctx, rasp, sched):
     """Word RASP, n = 250 (the general-n path), uniform Sec. 2.2 programs with
     the input-reading prologue, budget 10^6: every machine."""
@@ -500,7 +569,7 @@ def _to_width(b, w):
 
 
 @pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "persistent-hbm",
-                                   "firstpass-lds16-tiny-epoch", "ldsfirst-lds64"])
+                                   "firstpass-lds16-tiny-epoch", "ldsfirst-lds64", "hot8-tiny-epoch"])
 @pytest.mark.parametrize("isa", [0, 1])
 @pytest.mark.parametrize("w", [3, 5, 8, 16, 29])
 def test_narrow_words_bit_exact(ctx, rasp, sched, isa, w):

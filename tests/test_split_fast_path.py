@@ -45,17 +45,6 @@ def test_fast_path_positions_are_exact():
                             assert (got_np + 1 < P).all()
 
 
-def test_wrap_and_slot_end_are_not_fast():
-    """np = n - 1 (the operand wraps to word 0) and np + 1 = P (the operand in
-    HBM) both leave the common case."""
-    for n in range(2, 41):
-        for P in range(4, 45, 4):
-            lim = min(n, P)
-            assert max(0, n - 1, n) >= lim          # np = n - 1: np + 1 = n
-            if n > P:
-                assert max(0, P - 1, P) >= lim      # np = P - 1: np + 1 = P
-
-
 def test_common_positions_of_the_other_loops_are_exact():
     """Memory in HBM or whole in LDS: a lane is rare when j is outside [0, n),
     i is within 4 of the largest word, or n < 2; otherwise jj = j, the next

@@ -297,6 +297,10 @@ INFLIGHT_CANDIDATES = (1, 2, 4)
 # value depends on how many lanes a batch has
 INFLIGHT_FIRST_PASSES = (16, 64, 256)
 INFLIGHT_EPOCHS = (64, 256, 1024)
+# hot-cell runs: the misfits' waves per CU and the table size, tried again in
+# flight (on a CU share the misfits outnumber their lanes several times over)
+INFLIGHT_MISFIT_WAVES = (6, 8, 12, 16)
+INFLIGHT_HOT_CELLS = (16, 32)
 SERVE_PARTITIONS = 4
 
 
@@ -343,28 +347,32 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                     y0=torch.empty(N, dtype=torch.int32, device=dev),
                     y=torch.empty(ny, dtype=torch.int32, device=dev))
     outs = [new_outs() for _ in range(n)]
-    if ref_digest is not None:
-        # every machine's final memory, compared as its FNV-1a-64 digest
-        for o in outs:
-            o["mem_digest"] = torch.empty(N, dtype=torch.int64, device=dev)
+    # with a reference digest, each context's last timed batch is kept until
+    # after the timed region, when every machine's final memory is compared
+    # as its FNV-1a-64 digest (untimed)
+    kept = [None] * n
 
-    def drive(c, count, lat, errors):
+    def drive(c, count, lat, errors, keep_last):
         # one host thread per context: load, run, fetch, free, one batch after
         # another (the library's calls release the interpreter lock)
         try:
-            for _ in range(count):
+            for it in range(count):
                 t_issue = time.perf_counter()
                 h = R.rasp_load_batch(ctxs[c].handle, desc)
                 R.rasp_run(ctxs[c].handle, h, budget)
                 R.rasp_fetch_outputs_into(ctxs[c].handle, h, outs[c], device=True)
-                R.rasp_free_batch(ctxs[c].handle, h)
+                if keep_last and it == count - 1:
+                    kept[c] = h
+                else:
+                    R.rasp_free_batch(ctxs[c].handle, h)
                 lat.append(time.perf_counter() - t_issue)
         except Exception as e:                          # re-raised by run()
             errors.append(e)
 
-    def run(steps):
+    def run(steps, keep_last=False):
         lat, errors = [[] for _ in range(n)], []
-        threads = [threading.Thread(target=drive, args=(c, steps // n + (c < steps % n), lat[c], errors))
+        threads = [threading.Thread(target=drive, args=(c, steps // n + (c < steps % n), lat[c], errors,
+                                                        keep_last))
                    for c in range(n)]
         for t in threads:
             t.start()
@@ -381,7 +389,7 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
         R.rasp_kernel_times(c.handle)                   # reset
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    lat = run(steps)
+    lat = run(steps, keep_last=ref_digest is not None)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     # kernel times of the timed region, summed over the contexts (HIP events
@@ -400,9 +408,16 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
                     raise SystemExit("bench: NOT bit-exact with %d batches in flight: %s" % (n, k))
             if not np.array_equal(outs[c]["y"].cpu().numpy(), ref.Y):
                 raise SystemExit("bench: NOT bit-exact with %d batches in flight: output words" % n)
-            if ref_digest is not None and not np.array_equal(
-                    outs[c]["mem_digest"].cpu().numpy().view(np.uint64), ref_digest):
-                raise SystemExit("bench: NOT bit-exact with %d batches in flight: memory digests" % n)
+            if kept[c] is not None:
+                dg = {"mem_digest": torch.empty(N, dtype=torch.int64, device=dev)}
+                R.rasp_fetch_outputs_into(ctxs[c].handle, kept[c], dg, device=True)
+                R.rasp_free_batch(ctxs[c].handle, kept[c])
+                kept[c] = None
+                if not np.array_equal(dg["mem_digest"].cpu().numpy().view(np.uint64), ref_digest):
+                    raise SystemExit("bench: NOT bit-exact with %d batches in flight: memory digests" % n)
+    for c in range(n):
+        if kept[c] is not None:
+            R.rasp_free_batch(ctxs[c].handle, kept[c])
     for c in ctxs:
         if c is not ctx:
             c.close()
@@ -613,6 +628,10 @@ def main():
             ctx.set(R.RASP_OPT_FIRST_PASS, int(cached["inflight_first_pass"]))
         if args.epoch is None:
             ctx.set(R.RASP_OPT_EPOCH, int(cached["inflight_epoch"]))
+        if args.hot_cells is None and "inflight_hot_cells" in cached:
+            ctx.set(R.RASP_OPT_HOT_CELLS, int(cached["inflight_hot_cells"]))
+        if args.misfit_waves is None and "inflight_misfit_waves" in cached:
+            ctx.set(R.RASP_OPT_MISFIT_WAVES, int(cached["inflight_misfit_waves"]))
     if n_flight == 0:
         # batches in flight chosen like the other knobs: a short untimed trial
         # of each candidate (2n batches after n warm-up ones); a larger count
@@ -644,6 +663,11 @@ def main():
             retune.append(("first pass", R.RASP_OPT_FIRST_PASS, INFLIGHT_FIRST_PASSES))
         if args.epoch is None:
             retune.append(("epoch", R.RASP_OPT_EPOCH, INFLIGHT_EPOCHS))
+        if int(ctx.get(R.RASP_OPT_HOT_CELLS)) > 0:
+            if args.hot_cells is None:
+                retune.append(("hot cells", R.RASP_OPT_HOT_CELLS, INFLIGHT_HOT_CELLS))
+            if args.misfit_waves is None:
+                retune.append(("misfit waves", R.RASP_OPT_MISFIT_WAVES, INFLIGHT_MISFIT_WAVES))
         for name, opt, cands in retune:
             cur = int(ctx.get(opt))
             best = None
@@ -660,7 +684,10 @@ def main():
     if tuned is not None and cached is None and args.inflight == 0:
         tune_cache.put(cache_key, {"autotune": tuned, "inflight": n_flight,
                                    "inflight_first_pass": int(ctx.get(R.RASP_OPT_FIRST_PASS)),
-                                   "inflight_epoch": int(ctx.get(R.RASP_OPT_EPOCH))}, cache_path)
+                                   "inflight_epoch": int(ctx.get(R.RASP_OPT_EPOCH)),
+                                   "inflight_hot_cells": int(ctx.get(R.RASP_OPT_HOT_CELLS)),
+                                   "inflight_misfit_waves": int(ctx.get(R.RASP_OPT_MISFIT_WAVES))},
+                       cache_path)
     if n_flight > 1:
         inflight = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
                                   total_steps, n_flight,

@@ -261,6 +261,8 @@ struct HotMem {
     {
         rasp_lds[wb + 128u * s + half] = v;
     }
+    // LDS word index of word `half` of slot s
+    __device__ __forceinline__ uint32_t word(uint32_t s, uint32_t half) const { return wb + 128u * s + half; }
     __device__ __forceinline__ int32_t ld(uint32_t k) const
     {
         const uint32_t x = k >> 1, s = slot(x);
@@ -488,29 +490,36 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             const uint32_t jx = (st_en | need) ? jj : np;
             const uint32_t cf = np >> 1, cd = jx >> 1;
             const uint32_t sf = mem.slot(cf), sd = mem.slot(cd);
-            const int2 ef = mem.pair(sf), ed = mem.pair(sd);
-            // the common step reads the next instruction as one cell: an
-            // aligned np whose operand is word np + 1 (not wrapped to word 0
-            // or moved by i wrapping at the largest word)
-            bool cold = app | ((np & 1u) != 0u) | (nq != np + 1u) | (mem.tag(sf) != cf) | (mem.tag(sd) != cd);
-            if (!Tape::kLds) cold |= rd_ok;
+            // the next instruction's cell (both words), the data word itself
+            // (its LDS word index serves the store too) and both tags
+            const uint32_t dwi = mem.word(sd, jx & 1u);
+            const int2 ef = mem.pair(sf);
+            const int32_t dv = rasp_lds[dwi];
+            const uint32_t tf = mem.tag(sf), td = mem.tag(sd);
             // the slot reads stay beside the tag reads (one LDS round trip a
             // step) instead of sinking behind the test below, their only use
-            __asm__ volatile("" : : "v"(ef.x), "v"(ef.y), "v"(ed.x), "v"(ed.y));
-            if (__builtin_expect(any_lane(cold), 0)) {
+            __asm__ volatile("" : : "v"(ef.x), "v"(ef.y), "v"(dv));
+            // the common step reads the next instruction as one cell: an
+            // aligned np whose operand is word np + 1 (not wrapped to word 0
+            // or moved by i wrapping at the largest word); the wave takes it
+            // when no lane misses, appends an output word or reads the tape
+            uint64_t cold = __builtin_amdgcn_ballot_w64(app) | __builtin_amdgcn_ballot_w64((np & 1u) != 0u) |
+                            __builtin_amdgcn_ballot_w64(nq != np + 1u) | __builtin_amdgcn_ballot_w64(tf != cf) |
+                            __builtin_amdgcn_ballot_w64(td != cd);
+            if (!Tape::kLds) cold |= __builtin_amdgcn_ballot_w64(rd_ok);
+            if (__builtin_expect(cold != 0, 0)) {
                 if (Tape::kLds) w = rd_ok ? tv : a;
                 else if (rd_ok) w = tape.ld(u0);
                 mem.step(jj, w, st_en, need, np, nq, d, o, j);
                 out.st(y0, d, app);
             } else {
                 if (Tape::kLds) w = rd_ok ? tv : a;
-                const uint32_t half = jx & 1u;
-                if (st_en) mem.put(sd, half, w);
-                d = half ? ed.y : ed.x;
-                // a store into the next instruction's cell is seen by its fetch
-                const bool same = st_en & (sd == sf);
-                o = (same & (half == 0u)) ? w : ef.x;
-                j = (same & (half != 0u)) ? w : ef.y;
+                if (st_en) rasp_lds[dwi] = w;
+                d = dv;
+                // a store into the next instruction's words is seen by its
+                // fetch (both hit, so equal positions are the same LDS word)
+                o = (st_en & (jx == np)) ? w : ef.x;
+                j = (st_en & (jx == np + 1u)) ? w : ef.y;
             }
         } else {
             if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();

@@ -56,6 +56,8 @@ def test_cached_headline_knobs_find_a_traffic_record():
         knobs = {k: t[k] for k in ("schedule", "lds_words", "first_pass", "epoch", "waves_per_cu",
                                    "first_pass_kind", "hot_cells", "profile_steps", "misfit_waves")}
         knobs.update(first_pass=v["inflight_first_pass"], epoch=v["inflight_epoch"], c0_in_run=False)
+        knobs.update(hot_cells=v.get("inflight_hot_cells", knobs["hot_cells"]),
+                     misfit_waves=v.get("inflight_misfit_waves", knobs["misfit_waves"]))
         if v["inflight"] > 1:
             knobs.update(batches_in_flight=v["inflight"], cu_partition="split")
         assert counters.lookup(path, knobs, "persistent+misfit") is not None, knobs

@@ -63,6 +63,9 @@ def parse():
                     help="serve: servers, each with its own context on its own CU share (0: one "
                          "or four, whichever serves the closed loop faster)")
     ap.add_argument("--num-vms", type=int, default=0, help="override the population size")
+    ap.add_argument("--batch-file", default="",
+                    help="keep the generated batch in this .npz file and read it from there when it "
+                         "holds the same workload (saves generating it again, e.g. under a profiler)")
     ap.add_argument("--gen-workers", type=int, default=0,
                     help="processes generating the fig1 and rollout programs (0: up to 16; 1 under "
                          "a profiler, which would otherwise follow every child process)")
@@ -105,6 +108,19 @@ def parse():
 
 
 def make_batch(args):
+    from paper_2604_12902_amd import workloads as W
+    if args.batch_file and os.path.exists(args.batch_file):
+        b = W.load_batch(args.batch_file)
+        if b.meta.get("workload") == args.workload and (not args.num_vms or b.N == args.num_vms):
+            return b
+    b = _generate(args)
+    if args.batch_file:
+        b.meta["workload"] = args.workload
+        W.save_batch(b, args.batch_file)
+    return b
+
+
+def _generate(args):
     from paper_2604_12902_amd import workloads as W
     kw = {}
     if args.num_vms:

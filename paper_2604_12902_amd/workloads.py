@@ -424,3 +424,25 @@ def fig1(seed: int = 5, num_vms: int = 1 << 18, L: int = FIG1_L, budget: int = F
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+
+
+def save_batch(b: Batch, path: str) -> None:
+    """Write a batch to an .npz file (numpy arrays and a JSON header)."""
+    import json
+    header = json.dumps(dict(isa=int(b.isa), budget=int(b.budget), name=b.name, word_bits=int(b.word_bits),
+                             meta={k: v for k, v in b.meta.items() if isinstance(v, (int, float, str))}))
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, header=np.frombuffer(header.encode(), dtype=np.uint8), prog=b.prog, prog_off=b.prog_off,
+             mem_words=b.mem_words, tape=b.tape, tape_off=b.tape_off, tape_cap=b.tape_cap, out_cap=b.out_cap)
+    import os
+    os.replace(tmp, path)
+
+
+def load_batch(path: str) -> Batch:
+    """Read a batch written by save_batch (no pickled objects)."""
+    import json
+    with np.load(path, allow_pickle=False) as z:
+        h = json.loads(bytes(z["header"]).decode())
+        return Batch(h["isa"], z["prog"], z["prog_off"], z["mem_words"], z["tape"], z["tape_off"],
+                     z["tape_cap"], z["out_cap"], budget=h["budget"], name=h["name"], meta=h["meta"],
+                     word_bits=h["word_bits"])

@@ -68,3 +68,13 @@ def test_subset_roundtrip():
     for k, v in enumerate(idx):
         assert np.array_equal(s.prog[int(s.prog_off[k]):int(s.prog_off[k + 1])],
                               b.prog[int(b.prog_off[v]):int(b.prog_off[v + 1])])
+
+
+def test_batch_file_round_trip(tmp_path):
+    b = W.config3(num_vms=300, budget=777)
+    b.meta["workload"] = "uneven"
+    path = str(tmp_path / "b.npz")
+    W.save_batch(b, path)
+    c = W.load_batch(path)
+    assert c.sha256() == b.sha256() and c.budget == 777 and c.name == b.name
+    assert c.meta["workload"] == "uneven" and c.isa == b.isa and c.word_bits == 32

@@ -153,7 +153,6 @@ hipError_t launch_check_words_off(const int32_t *w, const uint64_t *off, uint64_
 // and, when every memory fits and tapes are short, the tape); 0 for memory in HBM
 uint32_t slot_words(uint32_t lds_words, uint32_t max_n, uint32_t max_ell);
 constexpr uint32_t kTapeLdsMax = 64;     // tapes up to this many words are staged in LDS
-constexpr int kWriteGroup = 8;           // machines written back per batch of LDS reads
 hipError_t launch_zero_queue(QueueState *q, hipStream_t st);
 hipError_t launch_reset_head(QueueState *q, hipStream_t st);     // head = 0, counts kept
 void init_kernel_attributes();

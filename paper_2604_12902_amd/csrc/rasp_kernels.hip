@@ -114,17 +114,25 @@ struct GlobalMem {                       // every word in HBM
     }
 };
 
+// LDS slots are interleaved across the lanes of a wave: word k of lane l's
+// slot is LDS word wave_base + 64 k + l, so the bank a lane touches depends on
+// its lane alone and the 64 lanes of a wave never conflict, whatever
+// positions they read (lanes running similar programs in step would collide
+// in lane-contiguous slots).  `base` below is wave_base + l; word k is at
+// base + (k << 6).
+constexpr uint32_t kSlotShift = 6;       // log2 of the distance between a slot's consecutive words
+
 struct LdsMem {                          // whole memory in the lane's LDS slot (n <= P)
     static constexpr bool kLds = true;
     static constexpr bool kColdIO = false;
     static constexpr bool kHot = false;
-    uint32_t base;                       // word index of the slot in rasp_lds
-    uint32_t spare;                      // word index of the slot's spare word
-    __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
-    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool) const { return rasp_lds[base + k]; }
+    uint32_t base;                       // LDS word index of the machine's word 0
+    uint32_t spare;                      // index of the slot's spare word
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + (k << kSlotShift)]; }
+    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool) const { return ld(k); }
     __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
     {
-        rasp_lds[en ? base + k : spare] = v;
+        rasp_lds[en ? base + (k << kSlotShift) : spare] = v;
     }
     __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
                                          uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
@@ -146,23 +154,23 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     // that out of line
     static constexpr bool kColdIO = true;
     static constexpr bool kHot = false;
-    uint32_t base, P;
+    uint32_t base, P;                    // slot word k < P at base + (k << 6), the spare at k = P
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const
     {
         int32_t v;
-        if (k < P) v = rasp_lds[base + k]; else v = M[k];
+        if (k < P) v = rasp_lds[base + (k << kSlotShift)]; else v = M[k];
         return v;
     }
     __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
     {
         int32_t v = 0;
-        if (k < P) v = rasp_lds[base + k]; else if (need) v = M[k];
+        if (k < P) v = rasp_lds[base + (k << kSlotShift)]; else if (need) v = M[k];
         return v;
     }
     __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
     {
-        if (en) { if (k < P) rasp_lds[base + k] = v; else M[k] = v; }
+        if (en) { if (k < P) rasp_lds[base + (k << kSlotShift)] = v; else M[k] = v; }
     }
     // each access picks LDS or HBM per lane
     __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
@@ -181,12 +189,12 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     __device__ __forceinline__ void step_near(uint32_t jx, int32_t w, bool st_en, uint32_t np,
                                               int32_t &d, int32_t &o, int32_t &j) const
     {
-        int32_t *const pd = &rasp_lds[base + jx];
-        *(st_en ? pd : &rasp_lds[base + P]) = w;
+        int32_t *const pd = &rasp_lds[base + (jx << kSlotShift)];
+        *(st_en ? pd : &rasp_lds[base + (P << kSlotShift)]) = w;
         d = *pd;
-        const int32_t *const pn = &rasp_lds[base + np];
+        const int32_t *const pn = &rasp_lds[base + (np << kSlotShift)];
         o = pn[0];
-        j = pn[1];
+        j = pn[1u << kSlotShift];
     }
 };
 
@@ -301,10 +309,10 @@ struct TapeG {
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return T[k]; }
 };
 
-struct TapeL {
+struct TapeL {                           // tape word k at base + (k << 6) (interleaved slot)
     static constexpr bool kLds = true;
     uint32_t base;
-    __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + k]; }
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + (k << kSlotShift)]; }
 };
 
 // output words, appended in HBM
@@ -955,34 +963,42 @@ hipError_t launch_plain(const BatchTable *tab, uint64_t total, uint32_t cap, uin
 // ballot + popcount prefix ranks).
 // MODE 0: memory in HBM.  MODE 1: each live machine's whole memory is staged
 // in its lane's LDS slot of P words (every n <= P).  MODE 2: words [0, P) in
-// LDS, the rest in HBM.  Staging and write-back are cooperative: the whole
-// wave moves one machine's words at a time, 16 bytes a lane (1 KB per
-// instruction, coalesced), with four machines' loads in flight before their
-// writes; only machines that stored into LDS (or are new) are written back.
+// LDS, the rest in HBM.  Slots are interleaved across the wave's lanes (word
+// k of lane l at wave_base + 64 k + l).  Each lane stages and writes back its own machine: one direct load
+// (or 16-byte store) moves a word (four words) of every lane that has one to
+// move; only machines that stored into LDS (or are new) are written back.
 // Work item k is machine work[k] of the launch (or machine k when work is
 // null); machines have already applied `already` transitions this run.
 // With surv non-null the launch is a first pass: a machine runs at most `cap`
 // transitions, and one still running after them is written back and appended
 // to surv (its index in the launch) for a later launch.
-// TLDS (MODE 1 only): the tape (TL words) is staged in the slot too, after
-// the memory and four spare words (the first spare takes the stores that do
-// not happen).
+// Slot words past the memory: word P takes the stores that do not happen;
+// from P + 4 on (TLDS, MODE 1 only) the tape, TL words.
 // ---------------------------------------------------------------------------
 
 // four words as one 16-byte access; global and LDS views of it
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) v4i gv4i;
-// direct global-to-LDS loads: lane l's 4 (or 16) bytes from g land at LDS
-// word row + l (or row + 4 l); row is the same for every lane of the wave
+// direct global-to-LDS load: lane l's 4 bytes from g land at LDS word row +
+// l; row is the same for every lane of the wave
 typedef __attribute__((address_space(1))) void gv;
 typedef __attribute__((address_space(3))) void lv;
 __device__ __forceinline__ void dma4(const int32_t *g, uint32_t row)
 {
     __builtin_amdgcn_global_load_lds((const gv *)g, (lv *)&rasp_lds[row], 4, 0, 0);
 }
-__device__ __forceinline__ void dma16(const int32_t *g, uint32_t row)
+
+// the largest (smallest) x over the lanes of the wave, in a scalar register;
+// every lane of the wave takes part
+__device__ __forceinline__ uint32_t wave_max(uint32_t x)
 {
-    __builtin_amdgcn_global_load_lds((const gv *)g, (lv *)&rasp_lds[row], 16, 0, 0);
+    for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, static_cast<uint32_t>(__shfl_xor(static_cast<int>(x), o)));
+    return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
+}
+__device__ __forceinline__ uint32_t wave_min(uint32_t x)
+{
+    for (int o = kWave / 2; o > 0; o >>= 1) x = min(x, static_cast<uint32_t>(__shfl_xor(static_cast<int>(x), o)));
+    return static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(x)));
 }
 
 // ONE: the launch holds a single batch, so every lane's batch is tab->b[0]
@@ -999,8 +1015,8 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
     const uint32_t wib = threadIdx.x / kWave;
     const uint32_t TB = P + 4u;                            // tape offset in a slot
     const uint32_t SP = P + 4u + (TLDS ? TL : 0u);         // slot: memory, spares, tape
-    const uint32_t wave_base = wib * kWave * SP;           // word index of lane 0's slot
-    const uint32_t slot = wave_base + lane * SP;
+    const uint32_t wave_base = wib * kWave * SP;           // LDS word index of the wave's slots
+    const uint32_t slot = wave_base + lane;                 // this lane's slot word 0 (word k at + 64 k)
     // the survivor (or misfit) count written by the first pass, and the
     // list's claim counter
     if (work != nullptr) total = which ? q->misfits : q->survivors;
@@ -1065,90 +1081,64 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
             continue;
         }
         // ---- stage the claimed machines' low memory words into their slots ----
-        // Direct global-to-LDS loads: each lane's 16 (or 4) bytes land at the
-        // row's LDS base + 16 (or 4) x lane, so one instruction moves a 256-word
-        // row (64 words for a program not 16-byte aligned) without passing
-        // through registers.  Every claimed machine's rows are issued before a
-        // single wait, so a refill pays about one memory latency.
+        // Each claiming lane moves its own machine with direct global-to-LDS
+        // loads: one instruction moves word k of every claiming lane's source
+        // to LDS word wave_base + 64 k + lane, its slot word k.  The zeros of
+        // c0 are stored first (issued after a direct load they would wait for
+        // it), every load is issued before a single wait, so a refill pays
+        // about one memory latency.
         if (MODE != 0) {
             // what each claiming lane's copy reads: the packed program (c0 of a
             // new machine, Sec. 2.1: program words, then zeros) or its memory
             const int32_t *src = nullptr, *tsrc = nullptr;
-            uint32_t srclen = 0, cnt = 0, tlen = 0, al = 1;
+            uint32_t n4 = 0, cnt = 0, tlen = 0, tn = 0, el = 0;
             if (claimed) {
                 cnt = r.n < P ? r.n : P;
                 if (fresh) {
                     const uint64_t p0 = bp->prog_off[v], t0 = bp->tape_off[v];
                     src = bp->prog + p0;
-                    srclen = static_cast<uint32_t>(bp->prog_off[v + 1] - p0);
-                    al = ((reinterpret_cast<uintptr_t>(src) & 15u) == 0 && (srclen & 3u) == 0) ? 1u : 0u;
+                    const uint32_t srclen = static_cast<uint32_t>(bp->prog_off[v + 1] - p0);
+                    n4 = srclen < cnt ? srclen : cnt;           // words copied from the source
                     tsrc = bp->tape + t0;
                     tlen = static_cast<uint32_t>(bp->tape_off[v + 1] - t0);
                 } else {
-                    src = M;                                // 16-byte aligned, padded to 4 words
-                    srclen = (cnt + 3u) & ~3u;
+                    src = M;
+                    n4 = cnt;
                     tsrc = T;
                     tlen = r.ell;
                 }
+                if (TLDS) { el = r.ell; tn = tlen < el ? tlen : el; }
             }
-            const uint32_t fr = (claimed && fresh) ? 1u : 0u;
             const uint64_t claimed_mask = __ballot(claimed);
-            // plain LDS stores first (the zeros after a new machine's program
-            // and tape): issued after a direct load they would wait for it
-            uint64_t cm = claimed_mask;
-            while (cm) {
-                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
-                cm &= cm - 1ull;
-                const uint32_t C = bcast(cnt, L), SL = bcast(srclen, L), D = wave_base + L * SP;
-                const uint32_t n4 = SL < C ? SL : C;            // words copied from the source
-                // up to the next 16 bytes one word a lane, then 16 bytes a lane
-                const uint32_t z4 = (n4 + 3u) & ~3u;
-                if (lane < z4 - n4 && n4 + lane < C) rasp_lds[D + n4 + lane] = 0;
-                for (uint32_t k = z4 + 4u * lane; k < C; k += 4u * kWave)
-                    *reinterpret_cast<v4i *>(&rasp_lds[D + k]) = v4i{0, 0, 0, 0};
+            if (claimed_mask) {
+                const uint32_t zlo = wave_min(claimed ? n4 : 0xffffffffu), zhi = wave_max(cnt);
+                for (uint32_t k = zlo; k < zhi; ++k)
+                    if (k >= n4 && k < cnt) rasp_lds[slot + (k << kSlotShift)] = 0;
                 if (TLDS) {
-                    const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L);
-                    if (lane < EL && lane >= TN) rasp_lds[D + TB + lane] = 0;
+                    const uint32_t tlo = wave_min(claimed ? tn : 0xffffffffu), thi = wave_max(el);
+                    for (uint32_t e = tlo; e < thi; ++e)
+                        if (e >= tn && e < el) rasp_lds[slot + ((TB + e) << kSlotShift)] = 0;
                 }
+                const uint32_t kmax = wave_max(n4);
+                for (uint32_t k = 0; k < kmax; ++k)
+                    if (k < n4) dma4(src + k, wave_base + (k << kSlotShift));
+                if (TLDS) {
+                    const uint32_t tmax = wave_max(tn);
+                    for (uint32_t e = 0; e < tmax; ++e)
+                        if (e < tn) dma4(tsrc + e, wave_base + ((TB + e) << kSlotShift));
+                }
+                __builtin_amdgcn_s_waitcnt(0);                  // the direct loads have landed
             }
-            // then every direct load: the memory (or program) rows and the tape
-            cm = claimed_mask;
-            while (cm) {
-                const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(cm)) - 1);
-                cm &= cm - 1ull;
-                const uint32_t C = bcast(cnt, L), SL = bcast(srclen, L), D = wave_base + L * SP;
-                const uint32_t n4 = SL < C ? SL : C;
-                const int32_t *S = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(src), L));
-                if (bcast(al, L)) {
-                    for (uint32_t k0 = 0; k0 < n4; k0 += 4u * kWave)
-                        if (k0 + 4u * lane < n4) dma16(S + k0 + 4u * lane, D + k0);
-                } else {
-                    for (uint32_t k0 = 0; k0 < n4; k0 += kWave)
-                        if (k0 + lane < n4) dma4(S + k0 + lane, D + k0);
-                }
-                if (TLDS) {                                     // tape x 0^(l-|x|) into the slot
-                    const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L);
-                    const int32_t *TS = reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L));
-                    if (lane < EL && lane < TN) dma4(TS + lane, D + TB);
-                }
-            }
-            if (claimed_mask) __builtin_amdgcn_s_waitcnt(0);   // the direct loads have landed
-            // a new machine's tape and output in HBM: x 0^(l-|x|) (from the
-            // slot when staged there) and 0^s
-            uint64_t fm = __ballot(fr != 0);
+            // a new machine's tape and output in HBM: x 0^(l-|x|) and 0^s
+            uint64_t fm = __ballot(claimed && fresh);
             while (fm) {
                 const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
                 fm &= fm - 1ull;
                 const uint32_t EL = bcast(r.ell, L), TN = bcast(tlen, L), SS = bcast(r.s, L);
-                const uint32_t D = wave_base + L * SP;
                 gi32 *TD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(T), L)));
                 gi32 *YD = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Y), L)));
-                if (TLDS) {
-                    if (lane < EL) TD[lane] = rasp_lds[D + TB + lane];
-                } else {
-                    const gi32 *TS = gptr(reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
-                    for (uint32_t e = lane; e < EL; e += kWave) TD[e] = e < TN ? TS[e] : 0;
-                }
+                const gi32 *TS = gptr(reinterpret_cast<const int32_t *>(bcast64(reinterpret_cast<uint64_t>(tsrc), L)));
+                for (uint32_t e = lane; e < EL; e += kWave) TD[e] = e < TN ? TS[e] : 0;
                 for (uint32_t e = lane; e < SS; e += kWave) YD[e] = 0;
             }
         }
@@ -1164,9 +1154,9 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
     (wm ? run_machine<ISA, POW2, true>(mm, tp, r, ou, lim, halted, ws)                         \
         : run_machine<ISA, POW2, false>(mm, tp, r, ou, lim, halted, 0u))
             if (MODE == 1) {
-                LdsMem mm{slot, slot + P};
+                LdsMem mm{slot, slot + (P << kSlotShift)};
                 if (TLDS) {
-                    TapeL tl{slot + TB};
+                    TapeL tl{slot + (TB << kSlotShift)};
                     OutG og{gptr(Y)};
                     t = RASP_RUN(mm, tl, og);
                 } else {
@@ -1198,36 +1188,28 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
             }
         }
         // ---- write back the slots of finished machines ----
+        // a machine that ran a step (or is new) may have stored: each such
+        // lane writes its own slot back, four words (16 bytes) at a time
+        // (memory slices are 16-byte aligned)
         if (MODE != 0) {
-            const uint32_t cnt = r.n < P ? r.n : P;
-            // a machine that ran a step (or is new) may have stored: its slot goes back
-            uint64_t fm = __ballot(finish && (done > 0 || fresh));
-            while (fm) {
-                // kWriteGroup machines: their LDS rows are read before any is stored
-                uint32_t C[kWriteGroup], D[kWriteGroup];
-                gi32 *MD[kWriteGroup];
-                uint32_t Cmax = 0;
-#pragma unroll
-                for (int u = 0; u < kWriteGroup; ++u) {
-                    C[u] = 0; D[u] = 0; MD[u] = nullptr;
-                    if (fm) {
-                        const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(fm)) - 1);
-                        fm &= fm - 1ull;
-                        C[u] = bcast(cnt, L);
-                        D[u] = wave_base + L * SP;
-                        MD[u] = gptr(reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(M), L)));
-                        Cmax = C[u] > Cmax ? C[u] : Cmax;
+            const bool back = finish && (done > 0 || fresh);
+            const uint32_t cnt = back ? (r.n < P ? r.n : P) : 0u;
+            const uint32_t kmax = wave_max(cnt);
+            if (kmax) {
+                gi32 *const MD = gptr(M);
+#pragma unroll 2
+                for (uint32_t k0 = 0; k0 < kmax; k0 += 4u) {
+                    if (k0 < cnt) {
+                        const int32_t *const ps = &rasp_lds[slot + (k0 << kSlotShift)];
+                        const v4i w{ps[0], ps[1u << kSlotShift], ps[2u << kSlotShift], ps[3u << kSlotShift]};
+                        if (k0 + 4u <= cnt) {
+                            *reinterpret_cast<gv4i *>(MD + k0) = w;
+                        } else {
+                            MD[k0] = w[0];
+                            if (k0 + 1u < cnt) MD[k0 + 1u] = w[1];
+                            if (k0 + 2u < cnt) MD[k0 + 2u] = w[2];
+                        }
                     }
-                }
-                for (uint32_t k0 = 0; k0 < Cmax; k0 += 4u * kWave) {
-                    const uint32_t k = k0 + 4u * lane;
-                    v4i w[kWriteGroup];
-#pragma unroll
-                    for (int u = 0; u < kWriteGroup; ++u)
-                        if (k < C[u]) w[u] = *reinterpret_cast<const v4i *>(&rasp_lds[D[u] + k]);
-#pragma unroll
-                    for (int u = 0; u < kWriteGroup; ++u)
-                        if (k < C[u]) *reinterpret_cast<gv4i *>(MD[u] + k) = w[u];
                 }
             }
         }

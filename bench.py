@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--loads", default="0.5,0.8,1.0", help="serve: offered load, fractions of capacity")
     ap.add_argument("--cap-gb", type=float, default=200.0, help="serve: arena footprint cap")
     ap.add_argument("--serve-epoch", type=int, default=4096, help="serve: transitions per epoch")
+    ap.add_argument("--serve-graph", type=int, default=0, choices=[0, 1],
+                    help="serve: replay each epoch's launch sequence as a HIP graph while the admitted set "
+                         "is unchanged (RASP_OPT_GRAPH)")
     ap.add_argument("--serve-partitions", type=int, default=0,
                     help="serve: servers, each with its own context on its own CU share (0: one "
                          "or four, whichever serves the closed loop faster)")
@@ -211,6 +214,8 @@ def serve_bench(args):
         else:
             cus = torch.cuda.get_device_properties(0).multi_processor_count
             state["ctxs"] = [R.Context(cap // k + (256 << 20), cus=R.cu_share(i, k, cus)) for i in range(k)]
+        for c in state["ctxs"]:
+            c.set(R.RASP_OPT_GRAPH, args.serve_graph)
         state["k"] = k
 
     def close_partitions():
@@ -272,7 +277,7 @@ def serve_bench(args):
             "data": "synthetic (seeded Poisson stream of random RASP programs)",
             "config": {"workload": "serving: Poisson stream, %d requests of 1,024-262,144 machines, "
                                    "budgets 4,096-65,536, cap %.1f GB" % (len(reqs), cap / 1e9),
-                       "epoch": args.serve_epoch, "partitions": parts},
+                       "epoch": args.serve_epoch, "partitions": parts, "graph": args.serve_graph},
             "closed_loop": {"requests_per_s": cap_qps, "steps_per_s": closed.steps_per_s,
                             "p50_ms": closed.p50_ms, "p99_ms": closed.p99_ms},
             "open_loop": runs}

@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define RASP_ABI_VERSION 3u
+#define RASP_ABI_VERSION 4u
 
 typedef struct rasp_ctx rasp_ctx;
 typedef uint64_t rasp_batch;                 /* 0 is never a valid handle */
@@ -87,7 +87,10 @@ enum {
 };
 
 /* rasp_outputs.flags */
-enum { RASP_OUT_DEVICE_PTRS = 1u };   /* every destination is device memory */
+enum {
+    RASP_OUT_DEVICE_PTRS = 1u,       /* every destination is device memory */
+    RASP_OUT_ASYNC = 2u              /* rasp_fetch_outputs queues the fetch and returns */
+};
 
 /*
  * rasp_create: open a context on HIP device `device`.
@@ -273,7 +276,18 @@ int rasp_sync(rasp_ctx *ctx, rasp_batch b);
 /*
  * rasp_fetch_outputs: wait for the batch's queued work, then copy the requested
  * fields into caller-owned buffers (layouts above).
- * Errors: STATE, DEVICE.
+ * With RASP_OUT_ASYNC in out->flags the fetch is queued on the context's copy
+ * stream (created on first use, on the context's compute units), behind the
+ * work already queued for the batch, and the call returns at once: the fields
+ * are in place when rasp_poll reports the batch done or rasp_sync returns.
+ * Host destinations must then be page-locked (hipHostMalloc, pinned torch
+ * tensors) for the copies to run in the background, and stay valid until
+ * then.  mem cannot be fetched this way.  Digests go through a buffer of the
+ * batch (8 bytes a machine of arena, taken at its first asynchronous fetch,
+ * returned with the batch).  Later runs of the batch are ordered after the
+ * fetch, and rasp_free_batch waits for it.  A serving loop hands one
+ * request's results back this way while the next epoch of the others runs.
+ * Errors: INVAL (mem with RASP_OUT_ASYNC), NOMEM (digest buffer), STATE, DEVICE.
  */
 int rasp_fetch_outputs(rasp_ctx *ctx, rasp_batch b, const rasp_outputs *out);
 
@@ -293,7 +307,23 @@ int rasp_batch_info(rasp_ctx *ctx, rasp_batch b, uint64_t *num_vms, uint64_t *me
  */
 int rasp_running_counts(rasp_ctx *ctx, const rasp_batch *bs, uint32_t k, uint64_t *counts);
 
-/* rasp_free_batch: release a batch's arena space after its queued work. */
+/*
+ * rasp_running_counts_async: queue the computation of rasp_running_counts for
+ * bs[0..k) behind the work queued so far on the context and return at once
+ * with a ticket; the counts land in page-locked memory of the context.
+ * rasp_running_counts_wait: wait until the counts of `ticket` are there and
+ * copy them to counts (k entries); a ticket is claimed once.  At most 4
+ * tickets are in flight per context: a fifth request waits for the oldest
+ * unclaimed one, which is then dropped (its wait fails with RASP_E_STATE).
+ * A serving loop queues the counts right behind an epoch's launch and does
+ * its host work (admission, loads, fetches) before it waits.
+ * Errors: INVAL (k, NULL pointers), STATE (bad handle or ticket), DEVICE.
+ */
+int rasp_running_counts_async(rasp_ctx *ctx, const rasp_batch *bs, uint32_t k, uint64_t *ticket);
+int rasp_running_counts_wait(rasp_ctx *ctx, uint64_t ticket, uint64_t *counts);
+
+/* rasp_free_batch: release a batch's arena space after its queued work (and
+ * after an asynchronous fetch of it still in flight, which it waits for). */
 int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
 
 /*

@@ -21,6 +21,8 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kTableRing = 16;
+constexpr int kTickets = 4;              // running-count requests in flight per context
+static_assert(sizeof(BatchTable) >= 8 * kMaxMulti * kTickets, "device count slots fit one table slot");
 constexpr uint64_t kStageWords = 32ull << 20;    // host-load staging: program + input words per chunk
 constexpr uint64_t kStageVms = 1ull << 20;       // and machines per chunk
 
@@ -88,6 +90,8 @@ struct Batch {
     bool uniform_dense = false;          // every n a multiple of 4: padded == dense
     bool status_stale = true;            // status not yet computed since the load
     hipEvent_t done = nullptr;           // recorded after the batch's latest queued work
+    bool fetch_pending = false;          // `done` was last recorded on the copy stream
+    Alloc fetch_tmp;                     // digests of asynchronous fetches (8 bytes a machine)
     ~Batch() { if (done) (void)hipEventDestroy(done); }
 };
 
@@ -178,7 +182,13 @@ struct rasp_ctx {
     uint64_t work_cap = 0;
     uint32_t *err_host = nullptr;        // pinned: error word and totals
     uint64_t *tot_host = nullptr;
-    uint64_t *count_host = nullptr;      // pinned: running counts
+    uint64_t *count_host = nullptr;      // pinned: running counts, kTickets x kMaxMulti
+    hipEvent_t count_ev[kTickets] = {};
+    uint64_t ticket_next = 1;            // ticket t uses slot t % kTickets
+    uint64_t ticket_of[kTickets] = {};   // the ticket a slot holds (0: none)
+    uint32_t ticket_k[kTickets] = {};
+    // copy stream (same CU mask as the first): asynchronous fetches
+    hipStream_t cstream = nullptr;
     // captured launch sequences (RASP_OPT_GRAPH)
     struct GraphEntry {
         std::vector<uint64_t> key;         // handles, budgets, knobs
@@ -258,6 +268,8 @@ Batch *find(rasp_ctx *c, rasp_batch b)
 template <class F> hipError_t timed_launch(rasp_ctx *c, int kind, F fn, hipStream_t st = nullptr);
 
 // Build c0 of a lazily loaded batch (RASP_DESC_LAZY) in the arena.
+int mark_queued(rasp_ctx *c, Batch *b);
+
 int materialize(rasp_ctx *c, Batch *b)
 {
     if (!b->dev.fresh) return RASP_OK;
@@ -266,7 +278,7 @@ int materialize(rasp_ctx *c, Batch *b)
         return launch_pack(d, d.prog, d.prog_off, d.tape, d.tape_off, c->stream); }));
     b->dev.fresh = 0;
     b->status_stale = true;
-    return RASP_OK;
+    return mark_queued(c, b);
 }
 
 hipEvent_t pooled_event(rasp_ctx *c)
@@ -651,6 +663,28 @@ int ensure_stream2(rasp_ctx *c)
     return RASP_OK;
 }
 
+// the copy stream, created on first use with the context's CU mask
+int ensure_cstream(rasp_ctx *c)
+{
+    if (c->cstream) return RASP_OK;
+    hipError_t e = c->cu_mask.empty()
+                       ? hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking)
+                       : hipExtStreamCreateWithCUMask(&c->cstream, static_cast<uint32_t>(c->cu_mask.size()),
+                                                      c->cu_mask.data());
+    if (e) return fail(c, RASP_E_DEVICE, "copy stream: %s", hipGetErrorString(e));
+    return RASP_OK;
+}
+
+// work about to be queued for b on the context stream comes after an
+// asynchronous fetch of b still in flight on the copy stream
+int after_fetch(rasp_ctx *c, Batch *b)
+{
+    if (!b->fetch_pending) return RASP_OK;
+    HIPCHK(c, hipStreamWaitEvent(c->stream, b->done, 0));
+    b->fetch_pending = false;
+    return RASP_OK;
+}
+
 // grab a device batch-table slot and its pinned host mirror
 int table_slot(rasp_ctx *c, BatchTable **host, BatchTable **devp, int *slot)
 {
@@ -686,6 +720,10 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k, co
     const uint32_t isa = bs[0]->dev.isa;
     for (uint32_t t = 1; t < k; ++t)
         if (bs[t]->dev.isa != isa) return fail(c, RASP_E_INVAL, "batches of one launch must share the instruction set");
+    for (uint32_t t = 0; t < k; ++t) {
+        int rc0 = after_fetch(c, bs[t]);
+        if (rc0) return rc0;
+    }
     // lazily loaded batches are built inside the persistent kernel when every
     // machine of the launch fits its LDS slot; otherwise c0 is packed first
     bool any_fresh = false;
@@ -1026,7 +1064,8 @@ int rasp_create(rasp_ctx **out, int device, void *arena, uint64_t arena_bytes, v
     }
     e = ok ? hipHostMalloc(reinterpret_cast<void **>(&c->host_tables), kTableRing * sizeof(BatchTable), hipHostMallocDefault) : hipErrorOutOfMemory;
     if (!e) e = hipHostMalloc(reinterpret_cast<void **>(&c->tot_host), 64, hipHostMallocDefault);
-    if (!e) e = hipHostMalloc(reinterpret_cast<void **>(&c->count_host), 8 * kMaxMulti, hipHostMallocDefault);
+    if (!e) e = hipHostMalloc(reinterpret_cast<void **>(&c->count_host), 8 * kMaxMulti * kTickets, hipHostMallocDefault);
+    for (int k = 0; k < kTickets && !e; ++k) e = hipEventCreateWithFlags(&c->count_ev[k], hipEventDisableTiming);
     for (int k = 0; k < kTableRing && !e; ++k) e = hipEventCreateWithFlags(&c->table_ev[k], hipEventDisableTiming);
     if (e) {
         rasp_destroy(c.release());
@@ -1076,6 +1115,7 @@ int rasp_destroy(rasp_ctx *c)
     if (!c) return RASP_OK;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->cstream) (void)hipStreamSynchronize(c->cstream);
     for (auto &g : c->graphs) if (g.exec) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
     for (int k = 0; k < kTableRing; ++k)
@@ -1093,6 +1133,9 @@ int rasp_destroy(rasp_ctx *c)
     }
     if (c->ev_first) (void)hipEventDestroy(c->ev_first);
     if (c->ev_second) (void)hipEventDestroy(c->ev_second);
+    if (c->cstream) (void)hipStreamDestroy(c->cstream);
+    for (int k = 0; k < kTickets; ++k)
+        if (c->count_ev[k]) (void)hipEventDestroy(c->count_ev[k]);
     delete c;
     return RASP_OK;
 }
@@ -1319,18 +1362,33 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
     Batch *b = find(c, h);
     if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)h);
     if (!o) return fail(c, RASP_E_INVAL, "outputs is NULL");
+    const bool async = (o->flags & RASP_OUT_ASYNC) != 0;
+    if (async && o->mem) return fail(c, RASP_E_INVAL, "memories are not fetched asynchronously");
+    if (async && (rc = ensure_cstream(c))) return rc;
     if ((rc = materialize(c, b))) return rc;
     hipStream_t st = c->stream;
     const hipMemcpyKind kind = (o->flags & RASP_OUT_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     const uint64_t N = b->N;
     if (o->status && b->status_stale) {
+        if ((rc = after_fetch(c, b))) return rc;
         HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_probe(b->dev, st); }));
         b->status_stale = false;
+        if ((rc = mark_queued(c, b))) return rc;
+    }
+    if (async) {
+        // the copy stream takes over behind the batch's own queued work (its
+        // event, recorded after its load, runs and probes), not behind work
+        // queued since for other batches
+        if (!b->done && (rc = mark_queued(c, b))) return rc;
+        if (!b->fetch_pending) HIPCHK(c, hipStreamWaitEvent(c->cstream, b->done, 0));
+        st = c->cstream;
+    } else if ((rc = after_fetch(c, b))) {
+        return rc;
     }
     if (kind == hipMemcpyDeviceToDevice) {
         if (o->status || o->steps || o->i || o->a || o->u0 || o->y0)
             HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] {
-                return launch_fetch_scalars(b->dev, o->status, o->steps, o->i, o->a, o->u0, o->y0, st); }));
+                return launch_fetch_scalars(b->dev, o->status, o->steps, o->i, o->a, o->u0, o->y0, st); }, st));
     } else {
         if (o->status) HIPCHK(c, hipMemcpyAsync(o->status, b->dev.status, N, kind, st));
         if (o->steps) HIPCHK(c, hipMemcpyAsync(o->steps, b->dev.steps, 8 * N, kind, st));
@@ -1343,7 +1401,15 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
     Alloc tmp;
     if (o->mem_digest) {
         if (kind == hipMemcpyDeviceToDevice) {
-            HIPCHK(c, timed_launch(c, RASP_KERNEL_DIGEST, [&] { return launch_digest(b->dev, o->mem_digest, st); }));
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_DIGEST, [&] { return launch_digest(b->dev, o->mem_digest, st); }, st));
+        } else if (async) {
+            // the batch's own digest buffer, kept (and reused by later
+            // asynchronous fetches) until the batch is released
+            if (!b->fetch_tmp.live && !arena_alloc(c, 8 * N, &b->fetch_tmp))
+                return fail(c, RASP_E_NOMEM, "arena cannot hold digests");
+            uint64_t *dd = at<uint64_t>(c, b->fetch_tmp);
+            HIPCHK(c, timed_launch(c, RASP_KERNEL_DIGEST, [&] { return launch_digest(b->dev, dd, st); }, st));
+            HIPCHK(c, hipMemcpyAsync(o->mem_digest, dd, 8 * N, kind, st));
         } else {
             if (!arena_alloc(c, 8 * N, &tmp)) return fail(c, RASP_E_NOMEM, "arena cannot hold digests");
             HIPCHK(c, timed_launch(c, RASP_KERNEL_DIGEST, [&] { return launch_digest(b->dev, at<uint64_t>(c, tmp), st); }));
@@ -1375,6 +1441,11 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
             arena_free(c, &tmp);
         }
     }
+    if (async) {
+        HIPCHK(c, hipEventRecord(b->done, st));
+        b->fetch_pending = true;
+        return RASP_OK;
+    }
     HIPCHK(c, hipStreamSynchronize(st));
     return RASP_OK;
 }
@@ -1401,25 +1472,38 @@ int rasp_batch_info(rasp_ctx *c, rasp_batch h, uint64_t *num_vms, uint64_t *mem_
     return RASP_OK;
 }
 
-int rasp_running_counts(rasp_ctx *c, const rasp_batch *hs, uint32_t k, uint64_t *counts)
+int rasp_running_counts_async(rasp_ctx *c, const rasp_batch *hs, uint32_t k, uint64_t *ticket)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (!hs || !counts || k == 0 || k > static_cast<uint32_t>(kMaxMulti))
-        return fail(c, RASP_E_INVAL, "rasp_running_counts takes 1..%d batches", kMaxMulti);
+    if (!hs || !ticket || k == 0 || k > static_cast<uint32_t>(kMaxMulti))
+        return fail(c, RASP_E_INVAL, "running counts take 1..%d batches and a ticket", kMaxMulti);
     hipStream_t st = c->stream;
+    Batch *bb[kMaxMulti];
+    for (uint32_t t = 0; t < k; ++t) {
+        bb[t] = find(c, hs[t]);
+        if (!bb[t]) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)hs[t]);
+    }
+    // the slot of this ticket: one still unclaimed there is waited for and dropped
+    const uint64_t tk = c->ticket_next;
+    const int s = static_cast<int>(tk % kTickets);
+    if (c->ticket_of[s]) {
+        HIPCHK(c, hipEventSynchronize(c->count_ev[s]));
+        c->ticket_of[s] = 0;
+    }
     BatchTable *ht, *dt;
     int slot;
     if ((rc = table_slot(c, &ht, &dt, &slot))) return rc;
     std::memset(ht, 0, sizeof(BatchTable));
     uint64_t total = 0;
     for (uint32_t t = 0; t < k; ++t) {
-        Batch *b = find(c, hs[t]);
-        if (!b) return fail(c, RASP_E_STATE, "unknown batch handle %llu", (unsigned long long)hs[t]);
+        Batch *b = bb[t];
         if ((rc = materialize(c, b))) return rc;
         if (b->status_stale) {
+            if ((rc = after_fetch(c, b))) return rc;
             HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_probe(b->dev, st); }));
             b->status_stale = false;
+            if ((rc = mark_queued(c, b))) return rc;
         }
         ht->b[t] = b->dev;
         ht->start[t] = total;
@@ -1427,16 +1511,43 @@ int rasp_running_counts(rasp_ctx *c, const rasp_batch *hs, uint32_t k, uint64_t 
     }
     ht->start[k] = total;
     ht->count = k;
-    unsigned long long *dcount = reinterpret_cast<unsigned long long *>(&c->tables[kTableRing]);
+    unsigned long long *dcount = reinterpret_cast<unsigned long long *>(&c->tables[kTableRing]) + s * kMaxMulti;
+    uint64_t *hcount = c->count_host + s * kMaxMulti;
     HIPCHK(c, hipMemcpyAsync(dt, ht, sizeof(BatchTable), hipMemcpyHostToDevice, st));
     HIPCHK(c, hipEventRecord(c->table_ev[slot], st));
     c->table_used[slot] = true;
     HIPCHK(c, hipMemsetAsync(dcount, 0, 8 * kMaxMulti, st));
     HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_running(dt, total, dcount, st); }));
-    HIPCHK(c, hipMemcpyAsync(c->count_host, dcount, 8 * k, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
-    std::memcpy(counts, c->count_host, 8 * k);
+    HIPCHK(c, hipMemcpyAsync(hcount, dcount, 8 * k, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipEventRecord(c->count_ev[s], st));
+    c->ticket_of[s] = tk;
+    c->ticket_k[s] = k;
+    ++c->ticket_next;
+    *ticket = tk;
     return RASP_OK;
+}
+
+int rasp_running_counts_wait(rasp_ctx *c, uint64_t ticket, uint64_t *counts)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!counts) return fail(c, RASP_E_INVAL, "counts is NULL");
+    const int s = static_cast<int>(ticket % kTickets);
+    if (ticket == 0 || c->ticket_of[s] != ticket)
+        return fail(c, RASP_E_STATE, "ticket %llu is unknown, already claimed or dropped (at most %d in flight)",
+                    (unsigned long long)ticket, kTickets);
+    HIPCHK(c, hipEventSynchronize(c->count_ev[s]));
+    std::memcpy(counts, c->count_host + s * kMaxMulti, 8 * c->ticket_k[s]);
+    c->ticket_of[s] = 0;
+    return RASP_OK;
+}
+
+int rasp_running_counts(rasp_ctx *c, const rasp_batch *hs, uint32_t k, uint64_t *counts)
+{
+    uint64_t tk = 0;
+    int rc = rasp_running_counts_async(c, hs, k, &tk);
+    if (rc) return rc;
+    return rasp_running_counts_wait(c, tk, counts);
 }
 
 int rasp_free_batch(rasp_ctx *c, rasp_batch h)
@@ -1444,6 +1555,8 @@ int rasp_free_batch(rasp_ctx *c, rasp_batch h)
     if (!c) return RASP_E_INVAL;
     auto it = c->batches.find(h);
     if (it == c->batches.end()) return fail(c, RASP_E_STATE, "unknown or freed batch handle %llu", (unsigned long long)h);
+    if (it->second->fetch_pending) HIPCHK(c, hipEventSynchronize(it->second->done));
+    arena_free(c, &it->second->fetch_tmp);
     drop_graphs(c, false, reinterpret_cast<uint64_t>(it->second.get()));
     // later work on the same stream may reuse the space only after this batch's
     // queued work: stream order guarantees it

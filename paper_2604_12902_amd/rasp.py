@@ -24,13 +24,14 @@ import torch  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librasp.so")
 
-RASP_ABI_VERSION = 3
+RASP_ABI_VERSION = 4
 RASP_OK, RASP_E_INVAL, RASP_E_NOMEM, RASP_E_DEVICE, RASP_E_STATE, RASP_E_BUSY = 0, -1, -2, -3, -4, -5
 RASP_ISA_WORD, RASP_ISA_CLASSIC = 0, 1
 RASP_RUNNING, RASP_HALTED = 0, 1
 RASP_DESC_DEVICE_PTRS = 1
 RASP_DESC_LAZY = 2
 RASP_OUT_DEVICE_PTRS = 1
+RASP_OUT_ASYNC = 2
 RASP_OPT_SCHEDULE, RASP_OPT_EPOCH, RASP_OPT_LDS_WORDS = 1, 2, 3
 RASP_OPT_WAVES_PER_CU, RASP_OPT_GRAPH, RASP_OPT_FIRST_PASS = 4, 5, 6
 RASP_SCHED_AUTO, RASP_SCHED_PLAIN, RASP_SCHED_PERSISTENT = 0, 1, 2
@@ -45,7 +46,8 @@ EXPORTED = ("rasp_create", "rasp_create_on_cus", "rasp_destroy", "rasp_last_erro
             "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi", "rasp_run_noalloc",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
             "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
-            "rasp_kernel_times", "rasp_running_counts", "rasp_autotune")
+            "rasp_kernel_times", "rasp_running_counts", "rasp_running_counts_async",
+            "rasp_running_counts_wait", "rasp_autotune")
 
 _ERRNAMES = {RASP_E_INVAL: "RASP_E_INVAL", RASP_E_NOMEM: "RASP_E_NOMEM",
              RASP_E_DEVICE: "RASP_E_DEVICE", RASP_E_STATE: "RASP_E_STATE",
@@ -102,6 +104,8 @@ def load_library(path: str = LIB_PATH):
         "rasp_device_info": ([P, P, P, P], i32),
         "rasp_kernel_times": ([P, P, P], i32),
         "rasp_running_counts": ([P, P, u32, P], i32),
+        "rasp_running_counts_async": ([P, P, u32, ctypes.POINTER(u64)], i32),
+        "rasp_running_counts_wait": ([P, u64, P], i32),
         "rasp_autotune": ([P, u64, u64, u64, P, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -290,6 +294,55 @@ def rasp_running_counts(ctx, batches) -> np.ndarray:
     hs = np.ascontiguousarray(batches, np.uint64)
     out = np.zeros(len(hs), np.uint64)
     _check(_lib.rasp_running_counts(ctx, _ptr(hs), len(hs), _ptr(out)), ctx)
+    return out
+
+
+def rasp_running_counts_async(ctx, batches) -> tuple:
+    """Queue the running counts of `batches`; returns (ticket, number of batches)."""
+    hs = np.ascontiguousarray(batches, np.uint64)
+    t = ctypes.c_uint64()
+    _check(_lib.rasp_running_counts_async(ctx, _ptr(hs), len(hs), ctypes.byref(t)), ctx)
+    return t.value, len(hs)
+
+
+def rasp_running_counts_wait(ctx, ticket: tuple) -> np.ndarray:
+    out = np.zeros(ticket[1], np.uint64)
+    _check(_lib.rasp_running_counts_wait(ctx, ticket[0], _ptr(out)), ctx)
+    return out
+
+
+def pinned_outputs(info: dict, digest: bool = True,
+                   fields=("status", "steps", "i", "a", "u0", "y0", "y")) -> dict:
+    """Page-locked host buffers (torch pinned tensors) for an asynchronous
+    fetch of a batch with rasp_batch_info `info`; numpy views of them stay
+    valid while the dict is alive."""
+    import torch
+    N = info["num_vms"]
+    dt = dict(status=torch.uint8, steps=torch.int64, i=torch.int32, a=torch.int32, u0=torch.int32,
+              y0=torch.int32)
+    out = {k: torch.empty(N, dtype=dt[k], pin_memory=True) for k in fields if k in dt}
+    if "y" in fields:
+        out["y"] = torch.empty(max(1, info["out_words"]), dtype=torch.int32, pin_memory=True)
+    if digest:
+        out["mem_digest"] = torch.empty(N, dtype=torch.int64, pin_memory=True)
+    return out
+
+
+def rasp_fetch_outputs_async(ctx, batch: int, dst: dict) -> None:
+    """Queue a fetch into page-locked host buffers (pinned_outputs); the
+    buffers are filled when rasp_poll(ctx, batch) reports the batch done."""
+    s = _outputs_struct(dst, RASP_OUT_ASYNC)
+    _check(_lib.rasp_fetch_outputs(ctx, batch, ctypes.byref(s)), ctx)
+
+
+def outputs_as_numpy(dst: dict, info: dict) -> dict:
+    """numpy copies of a completed asynchronous fetch, with the dtypes of
+    rasp_fetch_outputs."""
+    dt = dict(status=np.uint8, steps=np.uint64, i=np.int32, a=np.int32, u0=np.uint32, y0=np.uint32,
+              y=np.int32, mem_digest=np.uint64)
+    out = {k: v.numpy().view(dt[k]).copy() for k, v in dst.items()}
+    if "y" in out:
+        out["y"] = out["y"][:info["out_words"]]
     return out
 
 

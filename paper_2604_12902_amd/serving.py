@@ -15,6 +15,12 @@ all of them together, one epoch at a time:
     fixed point, is retired: its outputs are fetched to the host, its arena
     space is freed and the next arrivals can be admitted.
 
+With an executor that has the asynchronous calls (``running_async``,
+``fetch_async``) the host work overlaps the device: an epoch's running
+counts are queued right behind its launch, and while it runs the server
+collects the outputs of the previous epoch's retirees (fetched on the
+context's copy stream) and loads new arrivals; it waits only for the counts.
+
 Latency of a request = time its outputs are on the host - its arrival time.
 
 The executor is pluggable (``RaspExecutor`` drives the library; tests use a
@@ -117,6 +123,24 @@ class RaspExecutor:
     def free(self, handle) -> None:
         self.ctx.free(handle)
 
+    # asynchronous counterparts (the server overlaps host work with epochs)
+    def running_async(self, handles):
+        return self.R.rasp_running_counts_async(self.ctx.handle, handles)
+
+    def running_wait(self, ticket) -> np.ndarray:
+        return self.R.rasp_running_counts_wait(self.ctx.handle, ticket)
+
+    def fetch_async(self, handle):
+        info = self.R.rasp_batch_info(self.ctx.handle, handle)
+        dst = self.R.pinned_outputs(info)
+        self.R.rasp_fetch_outputs_async(self.ctx.handle, handle, dst)
+        return (handle, info, dst)
+
+    def fetch_wait(self, token) -> dict:
+        handle, info, dst = token
+        self.R.rasp_sync(self.ctx.handle, handle)
+        return self.R.outputs_as_numpy(dst, info)
+
 
 @dataclass
 class ServeStats:
@@ -156,19 +180,25 @@ class Server:
             q.footprint = self.ex.footprint(q.batch)
             if q.footprint > self.cap:
                 raise ValueError("request %d needs %d bytes, above the cap" % (q.rid, q.footprint))
-        queue, active = [], []
+        queue, active, fetching = [], [], []
         used = 0
         epochs = 0
         max_active = max_fp = 0
         t0 = self.clock() if start is None else start()
         k = 0
         n_done = 0
-        while n_done < len(pending):
+        asyn = hasattr(self.ex, "running_async")
+
+        def arrive():
+            nonlocal k
             now = self.clock() - t0
             while k < len(pending) and pending[k].arrival <= now:
                 queue.append(pending[k])
                 k += 1
-            # admission: FIFO while the footprint cap and the launch width allow
+
+        def admit():
+            # FIFO while the footprint cap and the launch width allow
+            nonlocal used, max_active, max_fp
             while queue and used + queue[0].footprint <= self.cap and len(active) < self.max_batches:
                 q = queue.pop(0)
                 q.handle = self.ex.load(q.batch)
@@ -178,29 +208,58 @@ class Server:
                 active.append(q)
             max_active = max(max_active, len(active))
             max_fp = max(max_fp, used)
+
+        def finish(q, result):
+            # outputs on the host: the request is done, its space free
+            nonlocal used, n_done
+            q.result = result
+            q.steps = int(np.asarray(q.result["steps"]).sum())
+            self.ex.free(q.handle)
+            q.done = self.clock() - t0
+            used -= q.footprint
+            n_done += 1
+
+        def collect():
+            for q, token in fetching:
+                finish(q, self.ex.fetch_wait(token))
+            fetching.clear()
+
+        while n_done < len(pending):
+            arrive()
+            admit()
             if not active:
+                if fetching:
+                    collect()
+                    continue
                 if k < len(pending):
                     wait = pending[k].arrival - (self.clock() - t0)
                     if wait > 0:
                         self.sleep(wait)
                 continue
-            budgets = [min(q.remaining, self.epoch) for q in active]
-            self.ex.run([q.handle for q in active], budgets)
+            launched = list(active)
+            budgets = [min(q.remaining, self.epoch) for q in launched]
+            self.ex.run([q.handle for q in launched], budgets)
             epochs += 1
-            running = self.ex.running([q.handle for q in active])
-            still = []
-            for q, b, nrun in zip(active, budgets, running):
+            if asyn:
+                ticket = self.ex.running_async([q.handle for q in launched])
+                # while the epoch runs: the previous retirees' outputs, then
+                # the arrivals their space admits (loaded behind the epoch)
+                collect()
+                arrive()
+                admit()
+                running = self.ex.running_wait(ticket)
+            else:
+                running = self.ex.running([q.handle for q in launched])
+            retired = set()
+            for q, b, nrun in zip(launched, budgets, running):
                 q.remaining -= b
                 if q.remaining == 0 or int(nrun) == 0:
-                    q.result = self.ex.fetch(q.handle)
-                    q.steps = int(np.asarray(q.result["steps"]).sum())
-                    self.ex.free(q.handle)
-                    q.done = self.clock() - t0
-                    used -= q.footprint
-                    n_done += 1
-                else:
-                    still.append(q)
-            active = still
+                    retired.add(id(q))
+                    if asyn:
+                        fetching.append((q, self.ex.fetch_async(q.handle)))
+                    else:
+                        finish(q, self.ex.fetch(q.handle))
+            active[:] = [q for q in active if id(q) not in retired]
         wall = self.clock() - t0
         if not pending:
             return ServeStats(0, wall, 0, epochs, 0.0, 0.0, 0.0, 0, 0, [])

@@ -16,14 +16,19 @@ def test_served_results_equal_standalone_runs():
     assert torch.cuda.is_available()
     reqs = serving.poisson_requests(14, qps=400.0, seed=11, size_lo=1024, size_hi=20000,
                                     budget_lo=256, budget_hi=4096)
-    ctx = R.Context(1 << 30)
+    # and one request at the largest size and budget of the serving stream:
+    # 262,144 uneven machines, budget 65,536, arriving among the others
+    big = serving.Request(14, reqs[5].arrival, 3, 262144, 65536, 11 * 1000003 + 14)
+    big.batch = serving.make_batch(big.config, big.size, big.budget, big.seed)
+    reqs.append(big)
+    ctx = R.Context(6 << 30)
     ex = serving.RaspExecutor(ctx)
     fps = sorted(ex.footprint(q.batch) for q in reqs)
     cap = sum(fps[-3:])                                  # at most ~3 large requests resident
-    print("case: serving 14 requests cap=%d" % cap, flush=True)
+    print("case: serving 15 requests (one of 262144 machines, budget 65536) cap=%d" % cap, flush=True)
     stats = serving.Server(ex, cap, epoch=512).serve(reqs)
-    assert stats.requests == 14 and stats.max_footprint <= cap and stats.max_active >= 2
-    alone = R.Context(1 << 30)
+    assert stats.requests == 15 and stats.max_footprint <= cap and stats.max_active >= 2
+    alone = R.Context(6 << 30)
     for q in reqs:
         h = alone.load(q.batch)
         alone.run(h, q.budget)
@@ -75,3 +80,56 @@ def test_beaver_search_on_the_served_path_matches_the_oracle():
     assert res.programs == run and res.halted == len(halting)
     assert [(t, r, v) for t, r, v, _ in res.best] == sorted(halting, key=lambda e: (-e[0], e[1], e[2]))[:keep]
     assert res.decades == dec
+
+
+def test_async_running_counts_and_fetch_equal_the_waiting_calls():
+    """rasp_running_counts_async / _wait give what rasp_running_counts gives;
+    at most four tickets are in flight (a fifth request drops the oldest);
+    an asynchronous fetch into pinned buffers equals the waiting fetch, a
+    later run of the batch is ordered after it, and the batch can be freed
+    with the fetch still in flight."""
+    import torch
+    from paper_2604_12902_amd import rasp as R, workloads as W
+    assert torch.cuda.is_available()
+    print("case: async counts and fetch", flush=True)
+    bs = [W.config3(seed=40 + t, num_vms=3000 + 1000 * t, budget=4096) for t in range(3)]
+    ctx = R.Context(1 << 30)
+    hs = [ctx.load(b) for b in bs]
+    ctx.run_multi(hs, [300, 300, 300])
+    want = R.rasp_running_counts(ctx.handle, hs)
+    tickets = [R.rasp_running_counts_async(ctx.handle, hs) for _ in range(5)]
+    with pytest.raises(R.RaspError):
+        R.rasp_running_counts_wait(ctx.handle, tickets[0])          # dropped by the fifth
+    for t in tickets[1:]:
+        assert np.array_equal(R.rasp_running_counts_wait(ctx.handle, t), want)
+    with pytest.raises(R.RaspError):
+        R.rasp_running_counts_wait(ctx.handle, tickets[1])          # claimed once
+    for h in hs:
+        info = R.rasp_batch_info(ctx.handle, h)
+        dst = R.pinned_outputs(info)
+        R.rasp_fetch_outputs_async(ctx.handle, h, dst)
+        ctx.sync(h)
+        got = R.outputs_as_numpy(dst, info)
+        ref = ctx.fetch(h, digest=True)
+        for k in ("status", "steps", "i", "a", "u0", "y0", "y", "mem_digest"):
+            assert np.array_equal(got[k], ref[k]), (h, k)
+    # an asynchronous fetch, then a run: the fetch sees the state before it
+    h = hs[0]
+    info = R.rasp_batch_info(ctx.handle, h)
+    before = ctx.fetch(h, digest=True)
+    dst = R.pinned_outputs(info)
+    R.rasp_fetch_outputs_async(ctx.handle, h, dst)
+    ctx.run(h, 2000)
+    ctx.sync(h)
+    got = R.outputs_as_numpy(dst, info)
+    for k in ("steps", "i", "a", "mem_digest"):
+        assert np.array_equal(got[k], before[k]), k
+    after = ctx.fetch(h, digest=True)
+    assert after["steps"].sum() > before["steps"].sum()
+    # free with a fetch in flight
+    dst2 = R.pinned_outputs(R.rasp_batch_info(ctx.handle, hs[1]))
+    R.rasp_fetch_outputs_async(ctx.handle, hs[1], dst2)
+    ctx.free(hs[1])
+    ctx.free(hs[0])
+    ctx.free(hs[2])
+    ctx.close()

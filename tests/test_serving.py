@@ -164,3 +164,59 @@ def test_partitioned_serving_deals_requests_and_keeps_each_share_of_the_cap():
         assert np.array_equal(q.result["mem_digest"], oracle.digest(want))
         assert q.done >= q.admitted >= q.arrival
     assert stats.steps == sum(int(q.result["steps"].sum()) for q in reqs)
+
+
+class AsyncOracleExecutor(OracleExecutor):
+    """The double with the asynchronous calls: running counts come back
+    through a ticket, outputs through a fetch token; a request whose fetch is
+    in flight must not be run again, and is freed only after its fetch was
+    collected."""
+
+    def __init__(self, clock, cap):
+        super().__init__(clock, cap)
+        self.tickets, self.fetching, self.collected = {}, {}, set()
+        self.next_ticket = 1
+
+    def run(self, handles, budgets):
+        assert not (set(handles) & set(self.fetching)), "a request with a fetch in flight was run"
+        super().run(handles, budgets)
+
+    def running_async(self, handles):
+        t = self.next_ticket
+        self.next_ticket += 1
+        self.tickets[t] = self.running(handles)
+        return t
+
+    def running_wait(self, ticket):
+        return self.tickets.pop(ticket)
+
+    def fetch_async(self, h):
+        self.fetching[h] = self.fetch(h)
+        return h
+
+    def fetch_wait(self, token):
+        self.collected.add(token)
+        return self.fetching.pop(token)
+
+    def free(self, h):
+        assert h in self.collected and h not in self.fetching
+        super().free(h)
+
+
+def test_overlapped_serving_gives_the_standalone_results():
+    clock = FakeClock()
+    reqs = small_requests(n=20, qps=2000.0)
+    cap = 2 * max(64 * q.batch.N + 4 * q.batch.footprint_words() for q in reqs)
+    ex = AsyncOracleExecutor(clock, cap)
+    stats = serving.Server(ex, cap, epoch=50, clock=clock, sleep=clock.sleep).serve(reqs)
+    assert stats.requests == len(reqs) and ex.max_used <= cap
+    assert not ex.states and not ex.fetching and not ex.tickets
+    for q in reqs:
+        want = oracle.run(q.batch, q.budget)
+        for k in ("status", "steps", "i", "a", "u0", "y0"):
+            assert np.array_equal(q.result[k], getattr(want, k)), (q.rid, k)
+        assert np.array_equal(q.result["mem_digest"], oracle.digest(want))
+        assert q.done >= q.admitted >= q.arrival
+    order = sorted(reqs, key=lambda q: q.admitted)
+    assert [q.rid for q in order] == sorted(q.rid for q in reqs)     # FIFO
+    assert max(len(l) for l in ex.launches) >= 2

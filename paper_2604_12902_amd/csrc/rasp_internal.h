@@ -28,6 +28,10 @@ struct DevBatch {
     uint64_t *mem_off;                 // word offset of M_v in M
     uint64_t *t_off;                   // word offset of tape_v in T
     uint64_t *y_off;                   // word offset of y_v in Y
+    // words of M_v at or above hw[v] are zero and not stored (c0's zero tail
+    // before anything is written there); a multiple of 4, at most n_v
+    // rounded up to 4, which means every word is stored
+    uint32_t *hw;
     int32_t *M;
     int32_t *T;
     int32_t *Y;
@@ -159,6 +163,8 @@ void init_kernel_attributes();
 hipError_t launch_running(const BatchTable *tab, uint64_t total, unsigned long long *counts,
                           hipStream_t st);
 hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st);
+// every machine's zero tail stored (zero_fill) or declared stored: hw = n rounded up to 4
+hipError_t launch_tails(DevBatch b, bool zero_fill, hipStream_t st);
 // per-machine scalars into device buffers (null pointers skipped)
 hipError_t launch_fetch_scalars(DevBatch b, uint8_t *status, uint64_t *steps, int32_t *i, int32_t *a,
                                 uint32_t *u0, uint32_t *y0, hipStream_t st);

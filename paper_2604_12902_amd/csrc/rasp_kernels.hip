@@ -114,6 +114,56 @@ struct GlobalMem {                       // every word in HBM
     }
 };
 
+// round up to a multiple of 4 words
+__device__ __forceinline__ uint32_t up4(uint32_t x) { return (x + 3u) & ~3u; }
+
+// store zeros in words [hw, top) of M (both multiples of 4), 16 bytes a store
+__device__ __forceinline__ void zero_tail(gi32 *M, uint32_t hw, uint32_t top)
+{
+    typedef int32_t z4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) z4 gz4;
+    for (uint32_t x = hw; x < top; x += 4u) *reinterpret_cast<gz4 *>(M + x) = z4{0, 0, 0, 0};
+}
+
+// every word in HBM, c0's zero tail not yet stored: words at or above hw read
+// as zero; the first store there stores the whole tail first (hw becomes n
+// rounded up to 4, the slice's padded length)
+struct TailMem {
+    static constexpr bool kLds = false;
+    static constexpr bool kColdIO = false;
+    static constexpr bool kHot = false;
+    gi32 *M;
+    mutable uint32_t hw;
+    uint32_t top;                        // n rounded up to 4
+    __device__ __forceinline__ int32_t ld(uint32_t k) const
+    {
+        int32_t v = 0;
+        if (k < hw) v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
+    {
+        int32_t v = 0;
+        if (need & (k < hw)) v = M[k];
+        return v;
+    }
+    __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
+    {
+        if (en) {
+            if (k >= hw) { zero_tail(M, hw, top); hw = top; }
+            M[k] = v;
+        }
+    }
+    __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
+                                         uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
+    {
+        st(jj, w, st_en);
+        d = ld_data(jj, need);
+        o = ld(np);
+        j = ld(nq);
+    }
+};
+
 // LDS slots are interleaved across the lanes of a wave: word k of lane l's
 // slot is LDS word wave_base + 64 k + l, so the bank a lane touches depends on
 // its lane alone and the 64 lanes of a wave never conflict, whatever
@@ -224,23 +274,33 @@ struct ProfMem {
     static constexpr bool kHot = false;
     gi32 *M;
     uint32_t bm, stride;
+    mutable uint32_t hw;                 // as in TailMem
+    uint32_t top;
     __device__ __forceinline__ void mark(uint32_t k) const
     {
         const uint32_t x = k >> 1;
         atomicOr(reinterpret_cast<uint32_t *>(&rasp_lds[bm + (x >> 5) * stride]), 1u << (x & 31u));
     }
-    __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
+    __device__ __forceinline__ int32_t ld(uint32_t k) const
+    {
+        int32_t v = 0;
+        if (k < hw) v = M[k];
+        return v;
+    }
     __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
                                          uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
     {
         mark(np);
         mark(nq);
         if (st_en | need) mark(jj);
-        if (st_en) M[jj] = w;
+        if (st_en) {
+            if (jj >= hw) { zero_tail(M, hw, top); hw = top; }
+            M[jj] = w;
+        }
         d = 0;
-        if (need) d = M[jj];
-        o = M[np];
-        j = M[nq];
+        if (need & (jj < hw)) d = M[jj];
+        o = ld(np);
+        j = ld(nq);
     }
 };
 
@@ -567,6 +627,8 @@ __device__ __forceinline__ int batch_of(const BatchTable *tab, uint64_t g)
 
 // ---------------------------------------------------------------------------
 // K1: pack c0 (Sec. 2.1): M = P 0^(n-2m), T = x 0^(l-|x|), Y = 0^s, scalars 0.
+// Only the program words of M are stored (rounded up to 16 bytes); hw marks
+// where the zero tail begins, and the step loops read it as zeros.
 // One wave per 64 consecutive machines: the scalars and shapes are read and
 // written coalesced (lane = machine); then the wave walks its 64 machines and
 // copies each memory slice with 16-byte accesses (64 lanes x 4 words).
@@ -607,6 +669,7 @@ __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restr
             n = b.n[v]; ell = b.ell[v]; s = b.s[v];
             mo = b.mem_off[v]; to = b.t_off[v]; yo = b.y_off[v];
             b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0; b.status[v] = 0;
+            b.hw[v] = min(up4(plen), up4(n));
         }
         const uint32_t cnt = static_cast<uint32_t>(b.N - g < kWave ? b.N - g : kWave);
         // Every machine of the wave one row wide (n <= 256 words, l and s <=
@@ -639,8 +702,7 @@ __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restr
                     const uint64_t MO = bcast64(mo, L), TO = bcast64(to, L), YO = bcast64(yo, L);
                     const uint32_t PL = bcast(plen, L), TL = bcast(tlen, L);
                     const uint32_t NN = bcast(n, L), EL = bcast(ell, L), SS = bcast(s, L);
-                    const int4 w = k < PL ? x[u] : int4{0, 0, 0, 0};
-                    if (k < NN) *reinterpret_cast<int4 *>(b.M + MO + k) = w;     // slices are padded to 4 words
+                    if (k < PL && k < NN) *reinterpret_cast<int4 *>(b.M + MO + k) = x[u];   // slices are padded to 4 words
                     if (lane < EL) b.T[TO + lane] = lane < TL ? y[u] : 0;
                     if (lane < SS) b.Y[YO + lane] = 0;
                 }
@@ -653,7 +715,8 @@ __global__ __launch_bounds__(256) void k_pack(DevBatch b, const int32_t *__restr
             const int32_t *src = prog + P0;
             int32_t *M = b.M + MO;
             const bool aligned = (P0 & 3u) == 0;
-            for (uint32_t k = 4 * lane; k < NN; k += 4 * kWave) {
+            const uint32_t HW = min(up4(PL), up4(NN));
+            for (uint32_t k = 4 * lane; k < HW; k += 4 * kWave) {
                 int4 w;
                 if (aligned && k + 4 <= PL) {
                     w = *reinterpret_cast<const int4 *>(src + k);
@@ -692,7 +755,7 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     r.n = b.n[v]; r.ell = b.ell[v]; r.s = b.s[v];
     r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
     r.p = cmod(r.i, r.n);
-    GlobalMem g{gptr(b.M + b.mem_off[v])};
+    const TailMem g{gptr(b.M + b.mem_off[v]), b.hw[v], up4(r.n)};
     TapeG tg{gptr(b.T + b.t_off[v])};
     bool halted;
     run_machine<ISA, false, true>(g, tg, r, OutG{gptr(b.Y + b.y_off[v])}, 0u, halted, b.wshift);
@@ -831,7 +894,9 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             int32_t *D = reinterpret_cast<int32_t *>(bcast64(reinterpret_cast<uint64_t>(Md), L));
             const uint32_t PL = bcast(plen, L), NN = bcast(n, L);
             const bool al = (bcast64(p0, L) & 3u) == 0;
-            for (uint32_t kk = 4 * lane; kk < NN; kk += 4 * kWave) {
+            // the program words; the zero tail stays unstored (hw)
+            const uint32_t HW = min(up4(PL), up4(NN));
+            for (uint32_t kk = 4 * lane; kk < HW; kk += 4 * kWave) {
                 int4 w;
                 if (al && kk + 4 <= PL) {
                     w = *reinterpret_cast<const int4 *>(S + kk);
@@ -850,6 +915,7 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             for (uint32_t e = lane; e < EL; e += kWave) TD[e] = e < TL ? TS[e] : 0;
             for (uint32_t e = lane; e < SS; e += kWave) YD[e] = 0;
         }
+        if (fresh) b.hw[v] = min(up4(plen), up4(n));
         // the wave's own stores must be visible to its lanes' loads below
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -866,26 +932,41 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             }
             r.p = cmod(r.i, r.n);
             const uint32_t limit = cap < budget ? cap : budget;
-            GlobalMem m{gptr(b.M + b.mem_off[v])};
+            // the memory with its zero tail possibly unstored (hw)
+            const uint32_t top = up4(r.n);
+            const uint32_t hw0 = fresh ? min(up4(static_cast<uint32_t>(b.prog_off[v + 1] - b.prog_off[v])), top) : b.hw[v];
+            TailMem m{gptr(b.M + b.mem_off[v]), hw0, top};
             TapeG tg{gptr(b.T + b.t_off[v])};
             bool halted;
             const OutG og{gptr(b.Y + b.y_off[v])};
             uint32_t t;
+            uint32_t hw;
             if constexpr (PROF) {
                 // the last min(R, limit) transitions are profiled
                 for (uint32_t kk = 0; kk < hot.bw; ++kk) rasp_lds[threadIdx.x + kk * blockDim.x] = 0;
                 const uint32_t R = hot.R < limit ? hot.R : limit;
                 t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit - R, halted, b.wshift)
                        : run_machine<ISA, POW2, false>(m, tg, r, og, limit - R, halted, 0u);
+                hw = m.hw;
                 if (!halted && t == limit - R) {
-                    const ProfMem pm{gptr(b.M + b.mem_off[v]), threadIdx.x, blockDim.x};
+                    const ProfMem pm{gptr(b.M + b.mem_off[v]), threadIdx.x, blockDim.x, hw, top};
                     t += wm ? run_machine<ISA, POW2, true>(pm, tg, r, og, R, halted, b.wshift)
                             : run_machine<ISA, POW2, false>(pm, tg, r, og, R, halted, 0u);
+                    hw = pm.hw;
                 }
             } else {
                 t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, b.wshift)
                        : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, 0u);
+                hw = m.hw;
             }
+            // a machine handed to a later launch of this run has its whole
+            // memory stored (those launches read and write it in full)
+            const bool next = !halted && t == limit && limit < budget;
+            if (next && hw < top) {
+                zero_tail(gptr(b.M + b.mem_off[v]), hw, top);
+                hw = top;
+            }
+            if (hw != hw0) b.hw[v] = hw;
             if (t || fresh) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
                 b.steps[v] = fresh ? t : b.steps[v] + t;
@@ -1194,6 +1275,8 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
         if (MODE != 0) {
             const bool back = finish && (done > 0 || fresh);
             const uint32_t cnt = back ? (r.n < P ? r.n : P) : 0u;
+            // a new machine (every memory fits, MODE 1) leaves its whole memory stored
+            if (back && fresh) bp->hw[v] = up4(r.n);
             const uint32_t kmax = wave_max(cnt);
             if (kmax) {
                 gi32 *const MD = gptr(M);
@@ -1538,13 +1621,13 @@ __global__ __launch_bounds__(256) void k_digest(DevBatch b, uint64_t *__restrict
 {
     const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= b.N) return;
-    const uint32_t n = b.n[v];
+    const uint32_t n = b.n[v], hw = b.hw[v];
     const int32_t *M = b.M + b.mem_off[v];
     uint64_t h = 0xcbf29ce484222325ull;
     const uint64_t prime = 0x100000001b3ull;
     uint32_t k = 0;
     for (; k + 4 <= n; k += 4) {
-        const int4 w = *reinterpret_cast<const int4 *>(M + k);
+        const int4 w = k < hw ? *reinterpret_cast<const int4 *>(M + k) : int4{0, 0, 0, 0};
         const uint32_t ws[4] = {static_cast<uint32_t>(w.x), static_cast<uint32_t>(w.y),
                                 static_cast<uint32_t>(w.z), static_cast<uint32_t>(w.w)};
 #pragma unroll
@@ -1553,7 +1636,7 @@ __global__ __launch_bounds__(256) void k_digest(DevBatch b, uint64_t *__restrict
             for (int byte = 0; byte < 4; ++byte) { h ^= (ws[e] >> (8 * byte)) & 0xffu; h *= prime; }
     }
     for (; k < n; ++k) {
-        const uint32_t x = static_cast<uint32_t>(M[k]);
+        const uint32_t x = k < hw ? static_cast<uint32_t>(M[k]) : 0u;
 #pragma unroll
         for (int byte = 0; byte < 4; ++byte) { h ^= (x >> (8 * byte)) & 0xffu; h *= prime; }
     }
@@ -1567,6 +1650,28 @@ hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st)
 }
 
 // per-batch count of machines not at a fixed point
+// every machine's zero tail stored (zero_fill) or declared stored (its
+// memory was written whole by other means): hw = n rounded up to 4
+__global__ __launch_bounds__(256) void k_tails(DevBatch b, uint32_t zero_fill)
+{
+    const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= b.N) return;
+    const uint32_t top = up4(b.n[v]);
+    if (zero_fill) {
+        const uint32_t hw = b.hw[v];
+        if (hw >= top) return;
+        zero_tail(gptr(b.M + b.mem_off[v]), hw, top);
+    }
+    b.hw[v] = top;
+}
+
+hipError_t launch_tails(DevBatch b, bool zero_fill, hipStream_t st)
+{
+    if (b.N == 0) return hipSuccess;
+    k_tails<<<static_cast<unsigned>((b.N + 255) / 256), 256, 0, st>>>(b, zero_fill ? 1u : 0u);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_running(const BatchTable *__restrict__ tab, uint64_t total,
                                                  unsigned long long *__restrict__ counts)
 {

@@ -89,6 +89,7 @@ struct Batch {
     bool all_pow2 = false;               // every n a power of two
     bool uniform_dense = false;          // every n a multiple of 4: padded == dense
     bool status_stale = true;            // status not yet computed since the load
+    bool tails = false;                  // some memory's zero tail is not stored (hw below n)
     hipEvent_t done = nullptr;           // recorded after the batch's latest queued work
     bool fetch_pending = false;          // `done` was last recorded on the copy stream
     Alloc fetch_tmp;                     // digests of asynchronous fetches (8 bytes a machine)
@@ -97,13 +98,14 @@ struct Batch {
 
 uint64_t meta_bytes(uint64_t N)
 {
-    // i a u0 y0 (4 each) steps (8) status (1) n ell s (4 each) mem_off t_off y_off (8 each)
+    // i a u0 y0 (4 each) steps (8) status (1) n ell s (4 each) mem_off t_off y_off (8 each) hw (4)
     uint64_t b = 0;
     b += align_up(4 * N, kAlign) * 4;
     b += align_up(8 * N, kAlign);
     b += align_up(N, kAlign);
     b += align_up(4 * N, kAlign) * 3;
     b += align_up(8 * N, kAlign) * 3;
+    b += align_up(4 * N, kAlign);
     return b;
 }
 
@@ -123,6 +125,7 @@ void carve_meta(char *base, uint64_t N, DevBatch *d)
     d->mem_off = reinterpret_cast<uint64_t *>(take(8 * N));
     d->t_off = reinterpret_cast<uint64_t *>(take(8 * N));
     d->y_off = reinterpret_cast<uint64_t *>(take(8 * N));
+    d->hw = reinterpret_cast<uint32_t *>(take(4 * N));
     d->N = N;
 }
 
@@ -278,7 +281,17 @@ int materialize(rasp_ctx *c, Batch *b)
         return launch_pack(d, d.prog, d.prog_off, d.tape, d.tape_off, c->stream); }));
     b->dev.fresh = 0;
     b->status_stale = true;
+    b->tails = true;
     return mark_queued(c, b);
+}
+
+// store every zero tail of the batch that is not stored yet
+int store_tails(rasp_ctx *c, Batch *b)
+{
+    if (!b->tails) return RASP_OK;
+    HIPCHK(c, timed_launch(c, RASP_KERNEL_OTHER, [&] { return launch_tails(b->dev, true, c->stream); }));
+    b->tails = false;
+    return RASP_OK;
 }
 
 hipEvent_t pooled_event(rasp_ctx *c)
@@ -491,10 +504,12 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
             DevBatch view = B->dev;
             view.i += v0; view.a += v0; view.u0 += v0; view.y0 += v0; view.steps += v0; view.status += v0;
             view.n += v0; view.ell += v0; view.s += v0; view.mem_off += v0; view.t_off += v0; view.y_off += v0;
+            view.hw += v0;
             view.N = cn;
             if (!e) e = timed_launch(c, RASP_KERNEL_PACK, [&] { return launch_pack(view, pg, po, pg, to, st); });
             // the staging buffer and the host offset vectors are reused: wait
             if (!e) e = hipStreamSynchronize(st);
+            B->tails = true;
             v0 = v1;
         }
         if (e) { fail(c, RASP_E_DEVICE, "loading batch: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
@@ -540,6 +555,7 @@ int load_common(rasp_ctx *c, const rasp_batch_desc *d, std::unique_ptr<Batch> &o
             B->dev.fresh = 1;              // c0 is built by the first run (or on demand)
         } else {
             e = timed_launch(c, RASP_KERNEL_PACK, [&] { return launch_pack(B->dev, prog_dev, poff_dev, tape_dev, toff_dev, st); });
+            B->tails = true;
         }
         if (e) { fail(c, RASP_E_DEVICE, "pack: %s", hipGetErrorString(e)); return bail(RASP_E_DEVICE); }
         // scratch is only used by work queued before this point: stream order makes reuse safe
@@ -754,6 +770,17 @@ int run_batches(rasp_ctx *c, Batch **bs, const uint32_t *budgets, uint32_t k, co
             int rc = materialize(c, bs[t]);
             if (rc) return rc;
         }
+    // c0's zero tails: the plain pass reads unstored ones as zeros (and stores
+    // them for the machines it hands on); any other opening launch reads and
+    // writes whole memories, so they are stored first
+    const bool plain_first = schedq == RASP_SCHED_PLAIN || (!fused && !lds_first && c->first_pass > 0);
+    for (uint32_t t = 0; t < k; ++t) {
+        if (bs[t]->dev.fresh && pack_in_plain) bs[t]->tails = true;
+        if (!plain_first && !bs[t]->dev.fresh) {
+            int rc = store_tails(c, bs[t]);
+            if (rc) return rc;
+        }
+    }
     // queue counters: the context's, or the caller-independent scratch
     QueueState *const qs = rs ? rs->queue : c->queue;
     const bool graphed = c->graph && !any_fresh && !rs && c->hot_cells == 0;
@@ -1231,6 +1258,7 @@ int rasp_load_state(rasp_ctx *c, const rasp_batch_desc *d, const rasp_outputs *s
         if (!e) e = hipMemcpyAsync(dense, s->mem, 4 * b.sum_n, kind, st);
         if (!e) e = launch_scatter_words(dense, doff, b.dev.n, N, b.dev.M, b.dev.mem_off, st);
     }
+    if (!e) e = launch_tails(b.dev, false, st);            // every memory word is stored
     uint32_t *errw = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(c->tot_host) + 32);
     if (!e) { *errw = 0; }
     // the error word lives in the queue scratch to avoid another allocation
@@ -1419,6 +1447,7 @@ int rasp_fetch_outputs(rasp_ctx *c, rasp_batch h, const rasp_outputs *o)
         }
     }
     if (o->mem) {
+        if ((rc = store_tails(c, b))) return rc;
         if (b->uniform_dense) {
             HIPCHK(c, hipMemcpyAsync(o->mem, b->dev.M, 4 * b->sum_n, kind, st));
         } else {
@@ -1690,6 +1719,7 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         x->sum_n_pad = m_end; x->sum_ell = t_end; x->sum_s = y_end;
         x->max_n = b->max_n; x->max_ell = b->max_ell; x->all_pow2 = b->all_pow2;
         x->status_stale = b->status_stale;
+        x->tails = b->tails;
         x->wbits = b->wbits;
         if (!arena_alloc(c, meta_bytes(K), &x->meta) || !arena_alloc(c, words_bytes(m_end, t_end, y_end), &x->words)) {
             arena_free(c, &snap.meta); arena_free(c, &snap.words);
@@ -1723,6 +1753,7 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
         if (!e) e = hipMemcpyAsync(dst.steps, src.steps, 8 * K, k, st);
         if (!e) e = hipMemcpyAsync(dst.status, src.status, K, k, st);
         if (!e) e = copy_shapes(src, dst);
+        if (!e) e = hipMemcpyAsync(dst.hw, src.hw, 4 * K, k, st);
         if (!e) e = hipMemcpyAsync(dst.M, src.M, 4 * m_end, k, st);
         if (!e && t_end) e = hipMemcpyAsync(dst.T, src.T, 4 * t_end, k, st);
         if (!e && y_end) e = hipMemcpyAsync(dst.Y, src.Y, 4 * y_end, k, st);
@@ -1754,6 +1785,7 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
                 hipError_t x = copy_batch(snap.dev, trial.dev);
                 if (x) return fail(c, RASP_E_DEVICE, "autotune restore: %s", hipGetErrorString(x));
                 trial.status_stale = snap.status_stale;
+                trial.tails = snap.tails;
             }
             Batch *tb = &trial;
             HIPCHK(c, hipEventRecord(e0, st));
@@ -1777,12 +1809,9 @@ int rasp_autotune(rasp_ctx *c, rasp_batch h, uint64_t budget, uint64_t max_vms, 
     // k waves of a compute unit resident: programs that touch only their low
     // cells then run from LDS at a higher occupancy, and memories far larger
     // than any slot keep their hottest low words in LDS at the occupancy
-    // that hides the latency of the rest.  A slot of a multiple of 32 words
-    // would put the same word of every lane's slot in one LDS bank, so such a
-    // slot gives up 4 words.
+    // that hides the latency of the rest.
     for (int64_t k : {3, 4, 6, 8, 10, 12, 14, 16}) {
         int64_t Pk = (static_cast<int64_t>(c->lds_bytes) / (k * kWave * 4) - 4) & ~int64_t(3);
-        if ((Pk + 4) % 32 == 0) Pk -= 4;
         if (Pk > 0 && Pk < b->max_n && std::find(lds_c.begin(), lds_c.end(), Pk) == lds_c.end()) lds_c.push_back(Pk);
     }
     const std::vector<int64_t> fp_c = {0, 16, 64, 256}, ep_c = {16, 64, 256, 1024}, wv_c = {8, 16, 32},

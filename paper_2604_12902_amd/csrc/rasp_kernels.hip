@@ -117,24 +117,41 @@ struct GlobalMem {                       // every word in HBM
 // round up to a multiple of 4 words
 __device__ __forceinline__ uint32_t up4(uint32_t x) { return (x + 3u) & ~3u; }
 
-// store zeros in words [hw, top) of M (both multiples of 4), 16 bytes a store
-__device__ __forceinline__ void zero_tail(gi32 *M, uint32_t hw, uint32_t top)
+
+// bcast of a lane's value to the wave (defined with the pack kernel below)
+__device__ __forceinline__ uint32_t bcast(uint32_t x, uint32_t L);
+__device__ __forceinline__ uint64_t bcast64(uint64_t x, uint32_t L);
+
+// The lanes with f set store their zero tails [hw, top), the wave's active
+// lanes together on one machine at a time (a word a lane: this sits inside
+// step loops, where a wider store would hold more registers), and set
+// hw = top.  Every active lane takes part.
+__device__ __forceinline__ void store_tails(bool f, gi32 *M, uint32_t &hw, uint32_t top)
 {
-    typedef int32_t z4 __attribute__((ext_vector_type(4)));
-    typedef __attribute__((address_space(1))) z4 gz4;
-    for (uint32_t x = hw; x < top; x += 4u) *reinterpret_cast<gz4 *>(M + x) = z4{0, 0, 0, 0};
+    uint64_t m = __builtin_amdgcn_ballot_w64(f);
+    if (m == 0) return;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t act = __builtin_amdgcn_ballot_w64(true);
+    const uint32_t rank = __popcll(act & ((1ull << lane) - 1ull)), cnt = __popcll(act);
+    do {
+        const uint32_t L = static_cast<uint32_t>(__ffsll(static_cast<unsigned long long>(m)) - 1);
+        m &= m - 1ull;
+        gi32 *const ML = reinterpret_cast<gi32 *>(bcast64(reinterpret_cast<uint64_t>(M), L));
+        const uint32_t h = bcast(hw, L), t = bcast(top, L);
+        for (uint32_t x = h + rank; x < t; x += cnt) ML[x] = 0;
+    } while (m);
+    if (f) hw = top;
 }
 
 // every word in HBM, c0's zero tail not yet stored: words at or above hw read
-// as zero; the first store there stores the whole tail first (hw becomes n
-// rounded up to 4, the slice's padded length)
+// as zero; a store at k >= hw first stores zeros in words [hw, k] (up to a
+// multiple of 4), which become the new hw
 struct TailMem {
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
     static constexpr bool kHot = false;
     gi32 *M;
     mutable uint32_t hw;
-    uint32_t top;                        // n rounded up to 4
     __device__ __forceinline__ int32_t ld(uint32_t k) const
     {
         int32_t v = 0;
@@ -149,10 +166,9 @@ struct TailMem {
     }
     __device__ __forceinline__ void st(uint32_t k, int32_t v, bool en) const
     {
-        if (en) {
-            if (k >= hw) { zero_tail(M, hw, top); hw = top; }
-            M[k] = v;
-        }
+        const bool f = en & (k >= hw);
+        if (__builtin_expect(any_lane(f), 0)) store_tails(f, M, hw, up4(k + 1u));
+        if (en) M[k] = v;
     }
     __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
                                          uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
@@ -274,33 +290,23 @@ struct ProfMem {
     static constexpr bool kHot = false;
     gi32 *M;
     uint32_t bm, stride;
-    mutable uint32_t hw;                 // as in TailMem
-    uint32_t top;
     __device__ __forceinline__ void mark(uint32_t k) const
     {
         const uint32_t x = k >> 1;
         atomicOr(reinterpret_cast<uint32_t *>(&rasp_lds[bm + (x >> 5) * stride]), 1u << (x & 31u));
     }
-    __device__ __forceinline__ int32_t ld(uint32_t k) const
-    {
-        int32_t v = 0;
-        if (k < hw) v = M[k];
-        return v;
-    }
+    __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
     __device__ __forceinline__ void step(uint32_t jj, int32_t w, bool st_en, bool need, uint32_t np,
                                          uint32_t nq, int32_t &d, int32_t &o, int32_t &j) const
     {
         mark(np);
         mark(nq);
         if (st_en | need) mark(jj);
-        if (st_en) {
-            if (jj >= hw) { zero_tail(M, hw, top); hw = top; }
-            M[jj] = w;
-        }
+        if (st_en) M[jj] = w;
         d = 0;
-        if (need & (jj < hw)) d = M[jj];
-        o = ld(np);
-        j = ld(nq);
+        if (need) d = M[jj];
+        o = M[np];
+        j = M[nq];
     }
 };
 
@@ -755,7 +761,7 @@ __global__ __launch_bounds__(256) void k_probe(DevBatch b)
     r.n = b.n[v]; r.ell = b.ell[v]; r.s = b.s[v];
     r.i = b.i[v]; r.a = b.a[v]; r.u0 = b.u0[v]; r.y0 = b.y0[v];
     r.p = cmod(r.i, r.n);
-    const TailMem g{gptr(b.M + b.mem_off[v]), b.hw[v], up4(r.n)};
+    const TailMem g{gptr(b.M + b.mem_off[v]), b.hw[v]};
     TapeG tg{gptr(b.T + b.t_off[v])};
     bool halted;
     run_machine<ISA, false, true>(g, tg, r, OutG{gptr(b.Y + b.y_off[v])}, 0u, halted, b.wshift);
@@ -864,6 +870,11 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
     bool survive = false;
     int k = 0;
     uint64_t v = 0;
+    // the zero tail of a machine handed to a later launch of this run is
+    // stored after the step loop (those launches read and write whole
+    // memories), the wave's lanes together
+    bool tail_f = false, tail_v = false;
+    uint32_t tail_hw = 0;
     if (g < total) {
         k = batch_of(tab, g);
         v = g - tab->start[k];
@@ -933,9 +944,9 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             r.p = cmod(r.i, r.n);
             const uint32_t limit = cap < budget ? cap : budget;
             // the memory with its zero tail possibly unstored (hw)
-            const uint32_t top = up4(r.n);
-            const uint32_t hw0 = fresh ? min(up4(static_cast<uint32_t>(b.prog_off[v + 1] - b.prog_off[v])), top) : b.hw[v];
-            TailMem m{gptr(b.M + b.mem_off[v]), hw0, top};
+            const uint32_t hw0 = fresh ? min(up4(static_cast<uint32_t>(b.prog_off[v + 1] - b.prog_off[v])), up4(r.n))
+                                       : b.hw[v];
+            TailMem m{gptr(b.M + b.mem_off[v]), hw0};
             TapeG tg{gptr(b.T + b.t_off[v])};
             bool halted;
             const OutG og{gptr(b.Y + b.y_off[v])};
@@ -948,25 +959,24 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
                 t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit - R, halted, b.wshift)
                        : run_machine<ISA, POW2, false>(m, tg, r, og, limit - R, halted, 0u);
                 hw = m.hw;
-                if (!halted && t == limit - R) {
-                    const ProfMem pm{gptr(b.M + b.mem_off[v]), threadIdx.x, blockDim.x, hw, top};
+                // the profiled transitions read whole memories: the machines
+                // that reach them store their tails first
+                const bool prof = !halted && t == limit - R;
+                const uint32_t top = up4(r.n);
+                store_tails(prof && hw < top, gptr(b.M + b.mem_off[v]), hw, top);
+                if (prof) {
+                    const ProfMem pm{gptr(b.M + b.mem_off[v]), threadIdx.x, blockDim.x};
                     t += wm ? run_machine<ISA, POW2, true>(pm, tg, r, og, R, halted, b.wshift)
                             : run_machine<ISA, POW2, false>(pm, tg, r, og, R, halted, 0u);
-                    hw = pm.hw;
                 }
             } else {
                 t = wm ? run_machine<ISA, POW2, true>(m, tg, r, og, limit, halted, b.wshift)
                        : run_machine<ISA, POW2, false>(m, tg, r, og, limit, halted, 0u);
                 hw = m.hw;
             }
-            // a machine handed to a later launch of this run has its whole
-            // memory stored (those launches read and write it in full)
-            const bool next = !halted && t == limit && limit < budget;
-            if (next && hw < top) {
-                zero_tail(gptr(b.M + b.mem_off[v]), hw, top);
-                hw = top;
-            }
-            if (hw != hw0) b.hw[v] = hw;
+            tail_f = !halted && t == limit && limit < budget && hw < up4(b.n[v]);
+            tail_hw = hw;
+            tail_v = true;
             if (t || fresh) {
                 b.i[v] = r.i; b.a[v] = r.a; b.u0[v] = r.u0; b.y0[v] = r.y0;
                 b.steps[v] = fresh ? t : b.steps[v] + t;
@@ -978,6 +988,11 @@ __global__ __launch_bounds__(256) void k_plain(const BatchTable *__restrict__ ta
             b.i[v] = 0; b.a[v] = 0; b.u0[v] = 0; b.y0[v] = 0; b.steps[v] = 0; b.status[v] = 0;
         }
     }
+    {
+        gi32 *const tM = gptr(tail_f ? b.M + b.mem_off[v] : b.M);
+        store_tails(tail_f, tM, tail_hw, tail_f ? up4(b.n[v]) : 0u);
+    }
+    if (tail_v) b.hw[v] = tail_hw;
     if (PROF && surv != nullptr) {
         uint32_t c = 65536u;
         const bool fit = survive && hot_place(threadIdx.x, blockDim.x, hot, c);
@@ -1655,14 +1670,11 @@ hipError_t launch_digest(DevBatch b, uint64_t *out, hipStream_t st)
 __global__ __launch_bounds__(256) void k_tails(DevBatch b, uint32_t zero_fill)
 {
     const uint64_t v = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (v >= b.N) return;
-    const uint32_t top = up4(b.n[v]);
-    if (zero_fill) {
-        const uint32_t hw = b.hw[v];
-        if (hw >= top) return;
-        zero_tail(gptr(b.M + b.mem_off[v]), hw, top);
-    }
-    b.hw[v] = top;
+    const bool in = v < b.N;
+    const uint32_t top = in ? up4(b.n[v]) : 0u;
+    uint32_t hw = in ? b.hw[v] : 0u;
+    if (zero_fill) store_tails(in && hw < top, gptr(b.M + (in ? b.mem_off[v] : 0)), hw, top);
+    if (in) b.hw[v] = top;
 }
 
 hipError_t launch_tails(DevBatch b, bool zero_fill, hipStream_t st)

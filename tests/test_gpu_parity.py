@@ -348,6 +348,36 @@ def test_order_and_halves(ctx, rasp):
         assert np.array_equal(np.concatenate([lo[k], hi[k]]), full[k]), k
 
 
+def test_zero_tails_across_runs_and_schedules(ctx, rasp):
+    """c0's zero tails are left unstored at load: runs that change schedule
+    between them (the plain pass reading unstored words as zero and storing
+    a tail at its first write there; a persistent launch without a first
+    pass, which needs every tail stored first; hot-cell tables; the
+    no-allocation entry point) compose to the oracle's result, with digests
+    (read through the mark) and memories (tails stored first) equal."""
+    b = W.config3(num_vms=3000, seed=37, budget=4000)
+    print("case: zero tails across schedules N=%d" % b.N, flush=True)
+    h = ctx.load(b)
+    done = 0
+    for sched, budget, noalloc in (("plain", 40, False), ("persistent-hbm", 150, False),
+                                   ("firstpass-lds64", 300, True), ("hot16", 700, False),
+                                   ("persistent-lds156-split", 800, False)):
+        configure(ctx, rasp, sched)
+        if noalloc:
+            rasp.rasp_run_noalloc(ctx.handle, h, budget)
+        else:
+            ctx.run(h, budget)
+        done += budget
+        want = oracle.run(b, done)
+        got = ctx.fetch(h, digest=True, mem=False)
+        compare(got, want, mem=False)
+        assert np.array_equal(got["y"], want.Y), sched
+        assert np.array_equal(got["mem_digest"], oracle.digest(want)), sched
+    got = ctx.fetch(h, mem=True, digest=True)
+    compare(got, oracle.run(b, done))
+    ctx.free(h)
+
+
 def test_device_descriptor_and_digest(ctx, rasp):
     """A descriptor of device-resident arrays (ragged shapes) loads the same
     c0 as a host one; memory digests equal the oracle's FNV-1a hashes."""

@@ -242,6 +242,13 @@ int rasp_run(rasp_ctx *ctx, rasp_batch b, uint64_t budget);
 int rasp_run_multi(rasp_ctx *ctx, const rasp_batch *bs, const uint64_t *budgets, uint32_t k);
 
 /*
+ * rasp_run_async: the same call as rasp_run_multi under the name a serving
+ * loop uses for it (one launch over k batches, returning once queued; wait
+ * with rasp_poll / rasp_sync per batch or rasp_running_counts_async).
+ */
+int rasp_run_async(rasp_ctx *ctx, const rasp_batch *bs, const uint64_t *budgets, uint32_t k);
+
+/*
  * rasp_run_noalloc: rasp_run for callers that cannot allocate device memory
  * (code under stream capture, tight serving loops, harnesses that forbid
  * allocation).  The same kernels and results as rasp_run, but the queue
@@ -275,7 +282,11 @@ int rasp_sync(rasp_ctx *ctx, rasp_batch b);
 
 /*
  * rasp_fetch_outputs: wait for the batch's queued work, then copy the requested
- * fields into caller-owned buffers (layouts above).
+ * fields into caller-owned buffers (layouts above): each machine's
+ * configuration after the transitions applied so far, Phi^tau(c0) of Sec. 2
+ * (i, a, memory M, tape head u0, output head y0 and the output words y that
+ * PRINT appended, Sec. 1.1 and 2.1), whether it is at a fixed point (status:
+ * F of Sec. 1.1/2.1) and how many transitions it retired.
  * With RASP_OUT_ASYNC in out->flags the fetch is queued on the context's copy
  * stream (created on first use, on the context's compute units), behind the
  * work already queued for the batch, and the call returns at once: the fields

@@ -1320,6 +1320,11 @@ int rasp_run_multi(rasp_ctx *c, const rasp_batch *hs, const uint64_t *budgets, u
     return RASP_OK;
 }
 
+int rasp_run_async(rasp_ctx *c, const rasp_batch *hs, const uint64_t *budgets, uint32_t k)
+{
+    return rasp_run_multi(c, hs, budgets, k);
+}
+
 int rasp_run_noalloc(rasp_ctx *c, rasp_batch h, uint64_t budget)
 {
     int rc = check_ctx(c);

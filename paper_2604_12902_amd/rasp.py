@@ -43,7 +43,8 @@ RASP_OPT_MISFIT_WAVES = 11
 KERNEL_NAMES = ("pack", "plain", "persistent", "digest", "other", "first", "misfit")
 
 EXPORTED = ("rasp_create", "rasp_create_on_cus", "rasp_destroy", "rasp_last_error", "rasp_batch_footprint",
-            "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi", "rasp_run_noalloc",
+            "rasp_load_batch", "rasp_load_state", "rasp_run", "rasp_run_multi", "rasp_run_async",
+            "rasp_run_noalloc",
             "rasp_poll", "rasp_sync", "rasp_fetch_outputs", "rasp_batch_info",
             "rasp_free_batch", "rasp_set_option", "rasp_get_option", "rasp_device_info",
             "rasp_kernel_times", "rasp_running_counts", "rasp_running_counts_async",
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
                              ctypes.POINTER(u64)], i32),
         "rasp_run": ([P, u64, u64], i32),
         "rasp_run_multi": ([P, P, P, u32], i32),
+        "rasp_run_async": ([P, P, P, u32], i32),
         "rasp_run_noalloc": ([P, u64, u64], i32),
         "rasp_poll": ([P, u64, ctypes.POINTER(i32)], i32),
         "rasp_sync": ([P, u64], i32),
@@ -242,6 +244,12 @@ def rasp_run_multi(ctx, batches, budgets) -> None:
     hs = np.ascontiguousarray(batches, np.uint64)
     bs = np.ascontiguousarray(budgets, np.uint64)
     _check(_lib.rasp_run_multi(ctx, _ptr(hs), _ptr(bs), len(hs)), ctx)
+
+
+def rasp_run_async(ctx, batches, budgets) -> None:
+    hs = np.ascontiguousarray(batches, np.uint64)
+    bs = np.ascontiguousarray(budgets, np.uint64)
+    _check(_lib.rasp_run_async(ctx, _ptr(hs), _ptr(bs), len(hs)), ctx)
 
 
 def rasp_poll(ctx, batch: int = 0) -> bool:

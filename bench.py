@@ -91,6 +91,9 @@ def parse():
                          "flight, one context, stream and host thread each (1: one batch at a "
                          "time; 0: the best of 1, 2 and 4 in short untimed trials); the "
                          "one-batch run is always timed and reported as single_batch")
+    ap.add_argument("--inflight-shares", type=int, default=0,
+                    help="CU shares the batches in flight are spread over (0: one share per batch); "
+                         "with fewer shares than batches, batch k runs on share k mod shares")
     ap.add_argument("--inflight-cus", choices=["shared", "split"], default="split",
                     help="with --inflight N: all contexts share every CU, or each context's stream "
                          "gets its own contiguous 1/N of them")
@@ -347,7 +350,8 @@ def timed_inflight(args, R, torch, ctx, desc, batch, budget, arena, ref, total_s
         # units, so one batch's latency-bound tail does not share SIMDs with
         # the next batch's load and first pass
         cus = R.rasp_device_info(ctx.handle)["compute_units"]
-        ctxs = [R.Context(arena, cus=R.cu_share(k, n, cus)) for k in range(n)]
+        shares = args.inflight_shares if 0 < args.inflight_shares < n else n
+        ctxs = [R.Context(arena, cus=R.cu_share(k % shares, shares, cus)) for k in range(n)]
     else:
         ctxs = [ctx] + [R.Context(arena) for _ in range(n - 1)]
     for c in ctxs:

@@ -58,14 +58,18 @@ def uneven():
     return b, oracle.run(b, b.budget, threads=16)
 
 
-@pytest.mark.parametrize("slots", ["default", "split40", "split32"])
+@pytest.mark.parametrize("slots", ["default", "hot32", "split40", "split32"])
 def test_uneven_batch_every_machine(R, uneven, slots):
     """4,194,304 machines, n 64-1,024: default knobs (memories in HBM), the
-    40-word split slots at 16 waves per CU the autotuner picks for this
-    workload (first pass 64), and 32-word split slots."""
+    hot-cell tables the autotuner picks for this workload (32 slots, a
+    576-step first pass profiling its last 512, misfits at 6 waves per CU),
+    40-word split slots at 16 waves per CU (first pass 64), and 32-word
+    split slots."""
     b, want = uneven
     print("case: uneven N=%d slots=%s" % (b.N, slots), flush=True)
-    knobs = {"split40": {R.RASP_OPT_LDS_WORDS: 40, R.RASP_OPT_FIRST_PASS: 64, R.RASP_OPT_WAVES_PER_CU: 16},
+    knobs = {"hot32": {R.RASP_OPT_LDS_WORDS: 40, R.RASP_OPT_FIRST_PASS: 576, R.RASP_OPT_WAVES_PER_CU: 16,
+                       R.RASP_OPT_HOT_CELLS: 32, R.RASP_OPT_PROFILE_STEPS: 512, R.RASP_OPT_MISFIT_WAVES: 6},
+             "split40": {R.RASP_OPT_LDS_WORDS: 40, R.RASP_OPT_FIRST_PASS: 64, R.RASP_OPT_WAVES_PER_CU: 16},
              "split32": {R.RASP_OPT_LDS_WORDS: 32}}.get(slots)
     got, info = _run(R, b, knobs=knobs)
     _check_all(got, want, info)

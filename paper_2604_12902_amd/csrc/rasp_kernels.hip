@@ -86,13 +86,29 @@ __device__ __forceinline__ bool any_lane(bool x)
 // pointers known to address global memory: loads and stores compile to
 // global_* instructions instead of flat_* ones (which also wait on LDS)
 typedef __attribute__((address_space(1))) int32_t gi32;
+typedef __attribute__((address_space(1))) uint64_t gu64;
 __device__ __forceinline__ gi32 *gptr(int32_t *p) { return (gi32 *)p; }
 __device__ __forceinline__ const gi32 *gptr(const int32_t *p) { return (const gi32 *)p; }
+
+// The next instruction's two words from HBM: one 8-byte load of the cell
+// holding word np (memory slices are padded to a multiple of 4 words, so the
+// cell of the last word of an odd-sized memory is in bounds), and a second
+// load only for a lane whose operand is not the cell's second word.
+// Scattered loads cost the vector memory pipeline a request per lane.
+__device__ __forceinline__ void fetch_pair(const gi32 *M, uint32_t np, uint32_t nq, int32_t &o, int32_t &j)
+{
+    const uint64_t e = *reinterpret_cast<const gu64 *>(M + (np & ~1u));
+    const int32_t e0 = static_cast<int32_t>(static_cast<uint32_t>(e)), e1 = static_cast<int32_t>(e >> 32);
+    const bool odd = (np & 1u) != 0u, two = odd | (nq != np + 1u);
+    int32_t j2 = 0;
+    if (two) j2 = M[nq];
+    o = odd ? e1 : e0;
+    j = two ? j2 : e1;
+}
 
 struct GlobalMem {                       // every word in HBM
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
-    static constexpr bool kHot = false;
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return M[k]; }
     __device__ __forceinline__ int32_t ld_data(uint32_t k, bool need) const
@@ -109,8 +125,7 @@ struct GlobalMem {                       // every word in HBM
     {
         st(jj, w, st_en);
         d = ld_data(jj, need);
-        o = ld(np);
-        j = ld(nq);
+        fetch_pair(M, np, nq, o, j);
     }
 };
 
@@ -149,7 +164,6 @@ __device__ __forceinline__ void store_tails(bool f, gi32 *M, uint32_t &hw, uint3
 struct TailMem {
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
-    static constexpr bool kHot = false;
     gi32 *M;
     mutable uint32_t hw;
     __device__ __forceinline__ int32_t ld(uint32_t k) const
@@ -175,8 +189,16 @@ struct TailMem {
     {
         st(jj, w, st_en);
         d = ld_data(jj, need);
-        o = ld(np);
-        j = ld(nq);
+        // as fetch_pair; hw is a multiple of 4, so a cell lies wholly below
+        // it or wholly above
+        const uint32_t c0 = np & ~1u;
+        uint64_t e = 0;
+        if (c0 < hw) e = *reinterpret_cast<const gu64 *>(M + c0);
+        const int32_t e0 = static_cast<int32_t>(static_cast<uint32_t>(e)), e1 = static_cast<int32_t>(e >> 32);
+        const bool odd = (np & 1u) != 0u;
+        o = odd ? e1 : e0;
+        j = e1;
+        if (odd | (nq != np + 1u)) j = ld(nq);
     }
 };
 
@@ -191,7 +213,6 @@ constexpr uint32_t kSlotShift = 6;       // log2 of the distance between a slot'
 struct LdsMem {                          // whole memory in the lane's LDS slot (n <= P)
     static constexpr bool kLds = true;
     static constexpr bool kColdIO = false;
-    static constexpr bool kHot = false;
     uint32_t base;                       // LDS word index of the machine's word 0
     uint32_t spare;                      // index of the slot's spare word
     __device__ __forceinline__ int32_t ld(uint32_t k) const { return rasp_lds[base + (k << kSlotShift)]; }
@@ -219,7 +240,6 @@ struct SplitMem {                        // words [0, P) in LDS, the rest in HBM
     // word at or above P or needs the general positions, and lays all of
     // that out of line
     static constexpr bool kColdIO = true;
-    static constexpr bool kHot = false;
     uint32_t base, P;                    // slot word k < P at base + (k << 6), the spare at k = P
     gi32 *M;
     __device__ __forceinline__ int32_t ld(uint32_t k) const
@@ -287,7 +307,6 @@ constexpr uint32_t kHotCandidates = 64;
 struct ProfMem {
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
-    static constexpr bool kHot = false;
     gi32 *M;
     uint32_t bm, stride;
     __device__ __forceinline__ void mark(uint32_t k) const
@@ -305,8 +324,7 @@ struct ProfMem {
         if (st_en) M[jj] = w;
         d = 0;
         if (need) d = M[jj];
-        o = M[np];
-        j = M[nq];
+        fetch_pair(M, np, nq, o, j);
     }
 };
 
@@ -319,7 +337,6 @@ struct ProfMem {
 struct HotMem {
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
-    static constexpr bool kHot = true;
     uint32_t wb, tb, c, mask;
     gi32 *M;
     __device__ __forceinline__ uint32_t slot(uint32_t x) const { return hot_slot(x, c, mask); }
@@ -496,15 +513,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
             // jj = j only for j in [0, n); with w < 32 a jump target j < n can
             // also be the largest word, whose operand position i + 1 wraps.
             // (A split slot tests its lanes below, with its uncommon work.)
-            if constexpr (Mem::kHot) {
-                // as in the split slot: an operand outside [0, n) needs the
-                // general positions only for a lane that uses its data word
-                // or jumps to it (a LOAD immediate or a jump not taken does
-                // not); every position a hot-cell lookup takes is masked to
-                // its table, so the other lanes' raw operands are harmless
-                rare = ((static_cast<uint32_t>(j) >= n) & (st_en | need | taken)) | (i >= imax - 3) | (n < 2u);
-                if (WM) rare |= taken & (j >= imax - 3);
-            } else if constexpr (!Mem::kColdIO) {
+            if constexpr (!Mem::kColdIO) {
                 rare = (static_cast<uint32_t>(j) >= n) | (i >= imax - 3) | (n < 2u);
                 if (WM) rare |= j >= imax - 3;
             }
@@ -551,56 +560,16 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
                 if (Tape::kLds) w = rd_ok ? tv : a;
                 mem.step_near(jx, w, st_en, np, d, o, j);
             }
-        } else if constexpr (Mem::kHot) {
-            // the data cell (the fetched cell again for a lane without a data
-            // access) and the next instruction's cell are read with their
-            // tags; every lane hitting both, with an aligned fetch whose
-            // operand does not wrap and nothing else uncommon, takes the
-            // straight LDS step
-            // lanes that use an operand outside [0, n) take their Euclidean
-            // positions first (one wave-uniform test); the cells they name
-            // are then looked up like any other
-            if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();
-            const uint32_t jx = (st_en | need) ? jj : np;
-            const uint32_t cf = np >> 1, cd = jx >> 1;
-            const uint32_t sf = mem.slot(cf), sd = mem.slot(cd);
-            // the next instruction's cell (both words), the data word itself
-            // (its LDS word index serves the store too) and both tags
-            const uint32_t dwi = mem.word(sd, jx & 1u);
-            const int2 ef = mem.pair(sf);
-            const int32_t dv = rasp_lds[dwi];
-            const uint32_t tf = mem.tag(sf), td = mem.tag(sd);
-            // the slot reads stay beside the tag reads (one LDS round trip a
-            // step) instead of sinking behind the test below, their only use
-            __asm__ volatile("" : : "v"(ef.x), "v"(ef.y), "v"(dv));
-            // the common step reads the next instruction as one cell: an
-            // aligned np whose operand is word np + 1 (not wrapped to word 0
-            // or moved by i wrapping at the largest word); the wave takes it
-            // when no lane misses, appends an output word or reads the tape
-            uint64_t cold = __builtin_amdgcn_ballot_w64(app) | __builtin_amdgcn_ballot_w64((np & 1u) != 0u) |
-                            __builtin_amdgcn_ballot_w64(nq != np + 1u) | __builtin_amdgcn_ballot_w64(tf != cf) |
-                            __builtin_amdgcn_ballot_w64(td != cd);
-            if (!Tape::kLds) cold |= __builtin_amdgcn_ballot_w64(rd_ok);
-            if (__builtin_expect(cold != 0, 0)) {
-                if (Tape::kLds) w = rd_ok ? tv : a;
-                else if (rd_ok) w = tape.ld(u0);
-                mem.step(jj, w, st_en, need, np, nq, d, o, j);
-                out.st(y0, d, app);
-            } else {
-                if (Tape::kLds) w = rd_ok ? tv : a;
-                if (st_en) rasp_lds[dwi] = w;
-                d = dv;
-                // a store into the next instruction's words is seen by its
-                // fetch (both hit, so equal positions are the same LDS word)
-                o = (st_en & (jx == np)) ? w : ef.x;
-                j = (st_en & (jx == np + 1u)) ? w : ef.y;
-            }
         } else {
             if (!POW2 && __builtin_expect(any_lane(rare), 0)) general_positions();
             if (Tape::kLds) w = rd_ok ? tv : a;                // loaded one step ahead
             else if (rd_ok) w = tape.ld(u0);
             mem.step(jj, w, st_en, need, np, nq, d, o, j);
         }
+        // the stored word's register is not reused while the store may still
+        // read it: a reuse before the next instruction's loads would wait for
+        // the store to complete, a second memory round trip
+        __asm__ volatile("" : : "v"(w));
         u0 += rd_ok ? 1u : 0u;
         if (Tape::kLds) tv = tape.ld(u0);
 
@@ -610,7 +579,7 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
         if (WM) na = static_cast<uint32_t>(sext(na, ws));
         na = op == 1u ? static_cast<uint32_t>(jcur) : na;
         a = static_cast<int32_t>(na);
-        if constexpr (!Mem::kColdIO && !Mem::kHot) out.st(y0, d, app);
+        if constexpr (!Mem::kColdIO) out.st(y0, d, app);
         y0 += app ? 1u : 0u;
         i = ni;
         p = np;
@@ -619,6 +588,188 @@ __device__ __forceinline__ uint32_t run_machine(const Mem &mem, const Tape &tape
     halted = stuck<ISA>(static_cast<uint32_t>(o), j, a, i, u0, ell);
     r.i = i; r.a = a; r.p = p; r.u0 = u0; r.y0 = y0;
     return limit - left;
+}
+
+// the accumulator after opcode op: LOAD takes the operand j, ADD/SUB (MUL in
+// the word set) combine a with the data word d, wrapping at w bits
+template <int ISA, bool WM>
+__device__ __forceinline__ int32_t accumulate(uint32_t op, int32_t a, int32_t d, int32_t j, uint32_t ws)
+{
+    const uint32_t ua = static_cast<uint32_t>(a), ud = static_cast<uint32_t>(d);
+    uint32_t na = op == 3u ? (ISA == 1 ? ua - ud : ua * ud) : ua;
+    na = op == 2u ? ua + ud : na;
+    if (WM) na = static_cast<uint32_t>(sext(na, ws));
+    na = op == 1u ? static_cast<uint32_t>(j) : na;
+    return static_cast<int32_t>(na);
+}
+
+// The hot-cell step loop.  The active lanes of the wave take their
+// transitions together, at most L of them (L wave-uniform, counted in a
+// scalar register).  A lane's transition is common when
+//   * its opcode is LOAD, ADD, SUB/MUL, STORE, the conditional jump, JMP
+//     (classic set) or PRINT with the output full -- not HALT, READ, an
+//     unknown opcode or an append;
+//   * it is not a jump onto its own instruction (i' = i);
+//   * the next instruction's cell and, for ADD, SUB/MUL and STORE, the data
+//     cell are in the table (their tags match);
+//   * the next instruction sits at an even position whose operand follows it
+//     without wrapping, and (n not a power of two) i is not within 4 of the
+//     largest word.
+// An operand outside [0, n) that a lane uses as its data position or jump
+// target is reduced to its Euclidean remainder first (one wave-uniform test;
+// a multiply-high by a per-machine reciprocal, no division).
+// The inner loop takes common transitions while every lane has one: the
+// straight LDS step, with no test for a fixed point (none is common).  At a
+// transition that is not common for some lane, the outer loop tests every
+// lane for a fixed point exactly (stopping there if any lane sits on one) and
+// takes that one transition with general positions and per-access lookups,
+// as the general step loop does.  Returns the transitions taken, the same for
+// every active lane; `halted` says whether the lane now sits on a fixed point.
+template <int ISA, bool POW2, bool WM>
+__device__ __forceinline__ uint32_t run_hot(const HotMem &mem, const TapeG &tape, const OutG &out, Regs &r,
+                                            uint32_t L, bool &halted, uint32_t ws)
+{
+    // bit k: opcode k is common (opcodes above 31 are taken as 31); a memory
+    // of fewer than two words has no common transition
+    constexpr uint32_t kCommon = ISA == 1 ? 0x1beu : 0xbeu;
+    const uint32_t n = r.n, nm = r.n - 1u, ell = r.ell, s = r.s;
+    const int32_t imax = WM ? static_cast<int32_t>(0x7fffffffu >> ws) : INT32_MAX;
+    // Euclidean remainders by n (not a power of two, n >= 2): see below
+    uint32_t rinv = 0, big = 0;
+    if (!POW2 && n >= 2u) {
+        rinv = 0xffffffffu / n;
+        big = (0x80000000u / n + (0x80000000u % n != 0u)) * n;
+    }
+    uint32_t p = r.p, u0 = r.u0, y0 = r.y0;
+    int32_t i = r.i, a = r.a;
+    int32_t o = mem.ld(p);
+    int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
+    uint32_t k = 0;
+    for (;;) {
+        // PRINT is common while the output is full
+        const uint32_t coldops = n < 2u ? ~0u : (~kCommon | (y0 < s ? 0x80u : 0u));
+        for (; k < L; ++k) {
+            const uint32_t op = static_cast<uint32_t>(o);
+            bool taken;
+            if (ISA == 1) taken = (op == 8u) | ((op == 5u) & (a > 0));
+            else taken = (op == 5u) & (a != 0);
+            const uint32_t i2 = static_cast<uint32_t>(i) + 2u;
+            const int32_t ni = taken ? j : (WM ? sext(i2, ws) : static_cast<int32_t>(i2));
+            const bool uses = (op - 2u) < 3u;                // ADD, SUB/MUL, STORE
+            // j mod n: an operand outside [0, n) that a lane uses as its data
+            // position or jump target takes its Euclidean remainder (one
+            // wave-uniform test; the others' operands are left as they are)
+            uint32_t jm = static_cast<uint32_t>(j);
+            if (POW2) {
+                jm &= nm;
+            } else if (__builtin_expect(any_lane((jm >= n) & (uses | taken)), 0)) {
+                // a negative word is moved up by big (a multiple of n, at
+                // least 2^31) into [0, 2^32); rinv = floor((2^32 - 1) / n)
+                // gives the quotient of the unsigned word less at most one
+                const uint32_t u = static_cast<uint32_t>(j) + (j < 0 ? big : 0u);
+                const uint32_t rr = u - __umulhi(u, rinv) * n;
+                jm = rr >= n ? rr - n : rr;
+            }
+            // the next instruction's position, and the data position of a
+            // lane that uses its data word (else the next instruction's again)
+            uint32_t np;
+            if (POW2) {
+                np = taken ? jm : ((p + 2u) & nm);
+            } else {
+                const uint32_t q = p + 2u;
+                np = taken ? jm : min(q, q - n);
+            }
+            const uint32_t np1 = np + 1u;
+            const uint32_t opc = min(op, 31u);
+            const uint32_t jx = uses ? jm : np;
+            const uint32_t cf = np >> 1, cd = jx >> 1;
+            const uint32_t sf = mem.slot(cf), sd = mem.slot(cd);
+            const uint32_t dwi = mem.word(sd, jx & 1u);
+            const int2 ef = mem.pair(sf);
+            const int32_t dv = rasp_lds[dwi];
+            const uint32_t tf = mem.tag(sf), td = mem.tag(sd);
+            // the four reads issue together (one LDS round trip a step): the
+            // slot reads are not left behind the test of the tags
+            __builtin_amdgcn_sched_barrier(0);
+            // each condition's lane mask, ORed in scalar registers
+            const uint32_t bad = (tf ^ cf) | (td ^ cd) | (np & 1u) | ((coldops >> opc) & 1u);
+            uint64_t cold = __builtin_amdgcn_ballot_w64(bad != 0u) | __builtin_amdgcn_ballot_w64(ni == i);
+            if (!POW2) {
+                cold |= __builtin_amdgcn_ballot_w64(np1 == n) | __builtin_amdgcn_ballot_w64(i >= imax - 3);
+                if (WM) cold |= __builtin_amdgcn_ballot_w64(taken & (j >= imax - 3));
+            }
+            if (__builtin_expect(cold != 0, 0)) break;
+            // every cell hit: a store into the next instruction's words is
+            // seen by its fetch (equal positions are the same LDS word)
+            const bool st = op == 4u;
+            if (st) rasp_lds[dwi] = a;
+            const int32_t jcur = j;
+            o = (st & (jx == np)) ? a : ef.x;
+            j = (st & (jx == np1)) ? a : ef.y;
+            a = accumulate<ISA, WM>(op, a, dv, jcur, ws);
+            i = ni;
+            p = np;
+        }
+        if (k == L) break;
+        // a transition that is not common for some lane
+        const uint32_t op = static_cast<uint32_t>(o);
+        bool taken, valid;
+        if (ISA == 1) {
+            taken = (op == 8u) | ((op == 5u) & (a > 0));
+            valid = (op - 1u) < 8u;
+        } else {
+            taken = (op == 5u) & (a != 0);
+            valid = (op - 1u) < 7u;
+        }
+        const bool is_rd = op == 6u;
+        const bool rd_ok = is_rd & (u0 < ell);
+        if (any_lane(!valid | (is_rd & !rd_ok) | (taken & (j == i)))) break;
+        const bool st_en = (op == 4u) | rd_ok;
+        const bool need = (op == 2u) | (op == 3u) | (op == 7u);
+        const bool app = (op == 7u) & (y0 < s);
+        const uint32_t i2 = static_cast<uint32_t>(i) + 2u;
+        const int32_t ni = taken ? j : (WM ? sext(i2, ws) : static_cast<int32_t>(i2));
+        uint32_t jj, np, nq;
+        if (POW2) {
+            jj = static_cast<uint32_t>(j) & nm;
+            np = taken ? jj : ((p + 2u) & nm);
+            nq = (np + 1u) & nm;
+        } else {
+            // as in the general loop: the common positions, and the general
+            // ones for a lane that needs them
+            jj = static_cast<uint32_t>(j);
+            uint32_t q = p + 2u;
+            q = q >= n ? q - n : q;
+            np = taken ? jj : q;
+            nq = np + 1u;
+            nq = nq == n ? 0u : nq;
+            bool rare = ((static_cast<uint32_t>(j) >= n) & (st_en | need | taken)) | (i >= imax - 3) | (n < 2u);
+            if (WM) rare |= taken & (j >= imax - 3);
+            if (any_lane(rare)) {
+                const uint32_t jj2 = cmod(j, n);
+                const uint32_t np2 = taken ? jj2 : advance_pos(i, p, n, imax, WM ? ws : 0u);
+                const uint32_t nq2 = operand_pos(ni, np2, n, imax);
+                jj = rare ? jj2 : jj;
+                np = rare ? np2 : np;
+                nq = rare ? nq2 : nq;
+            }
+        }
+        int32_t w = a, d;
+        if (rd_ok) w = tape.ld(u0);
+        const int32_t jcur = j;
+        mem.step(jj, w, st_en, need, np, nq, d, o, j);
+        __asm__ volatile("" : : "v"(w));                  // as in the general loop
+        out.st(y0, d, app);
+        u0 += rd_ok ? 1u : 0u;
+        y0 += app ? 1u : 0u;
+        a = accumulate<ISA, WM>(op, a, d, jcur, ws);
+        i = ni;
+        p = np;
+        ++k;
+    }
+    halted = stuck<ISA>(static_cast<uint32_t>(o), j, a, i, u0, ell);
+    r.i = i; r.a = a; r.p = p; r.u0 = u0; r.y0 = y0;
+    return k;
 }
 
 __device__ __forceinline__ int batch_of(const BatchTable *tab, uint64_t g)
@@ -1392,12 +1543,16 @@ __device__ __forceinline__ void persistent_hot_body(const BatchTable *__restrict
     uint32_t done = 0, limit = 0, ws = 0, c = 65536u;
     uint64_t pos = 0, v = 0;
     const DevBatch *bp = nullptr;
+    uint32_t spent = 0;                  // transitions since the last refill (wave-uniform)
 
     for (;;) {
-        // ---- refill idle lanes from the queue ----
+        // ---- refill idle lanes from the queue, once an epoch (a lane that
+        // finishes earlier waits for the epoch's end) or when no lane runs ----
         const uint64_t idle = __ballot(!has);
         bool claimed = false;
-        if (idle != 0 && !exhausted) {
+        const bool due = spent >= epoch || idle == ~0ull;
+        if (due) spent = 0;
+        if (due && idle != 0 && !exhausted) {
             const int leader = __ffsll(static_cast<unsigned long long>(idle)) - 1;
             const uint32_t cnt = __popcll(idle);
             unsigned long long base = 0;
@@ -1455,17 +1610,18 @@ __device__ __forceinline__ void persistent_hot_body(const BatchTable *__restrict
         // the wave's table writes before its lanes' reads
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __builtin_amdgcn_wave_barrier();
-        // ---- run ----
+        // ---- run: the lanes step together until one of them reaches a
+        // fixed point or its budget, or the epoch ends ----
+        const uint32_t L = wave_min(has ? min(limit - done, epoch - spent) : ~0u);
         bool finish = false;
+        uint32_t t = 0;
         if (has) {
-            uint32_t lim = limit - done;
-            if (lim > epoch) lim = epoch;
             bool halted;
             const HotMem mm{wave_base + 2u * lane, tag_base + lane, c, mask, gptr(M)};
             const TapeG tg{gptr(T)};
             const OutG og{gptr(Y)};
-            const uint32_t t = wm ? run_machine<ISA, POW2, true>(mm, tg, r, og, lim, halted, ws)
-                                  : run_machine<ISA, POW2, false>(mm, tg, r, og, lim, halted, 0u);
+            t = wm ? run_hot<ISA, POW2, true>(mm, tg, og, r, L, halted, ws)
+                   : run_hot<ISA, POW2, false>(mm, tg, og, r, L, halted, 0u);
             done += t;
             if (halted || done == limit) {
                 if (done) {
@@ -1476,6 +1632,7 @@ __device__ __forceinline__ void persistent_hot_body(const BatchTable *__restrict
                 finish = true;
             }
         }
+        spent += wave_max(t);
         // ---- write the finished machines' cells back ----
         uint64_t fm = __ballot(finish);
         while (fm != 0) {

@@ -12,8 +12,9 @@ The value is the sum of retired transitions of a batch divided by the mean
 time per batch over the timed batches, with up to four batches in flight:
 one context per batch in flight, each with its own host thread and its own
 share of the compute units (rasp_create_on_cus), the count chosen from 1, 2
-and 4 by short untimed trials, after which the first-pass length and the
-epoch are tried again the same way in flight.  The same schedule one batch at a time
+and 4 by short untimed trials, after which the first-pass length, the epoch
+and the hot-cell knobs are tried again the same way in flight (and, when one
+of them moved, the other counts once more).  The same schedule one batch at a time
 (single_batch) and the plain one-machine-per-lane schedule are reported
 beside it.  Before reporting, the final state of every machine is checked
 against the CPU oracle (the oracle is run on the same batch on the host; its
@@ -693,6 +694,8 @@ def main():
                 retune.append(("hot cells", R.RASP_OPT_HOT_CELLS, INFLIGHT_HOT_CELLS))
             if args.misfit_waves is None:
                 retune.append(("misfit waves", R.RASP_OPT_MISFIT_WAVES, INFLIGHT_MISFIT_WAVES))
+        moved = False
+        last = None
         for name, opt, cands in retune:
             cur = int(ctx.get(opt))
             best = None
@@ -706,6 +709,23 @@ def main():
                 if best is None or rate > best[1] / 0.97:
                     best = (v, rate)
             ctx.set(opt, best[0])
+            moved |= best[0] != cur
+            last = best[1]
+        # a knob that moved can change which count in flight is best (a
+        # table size chosen one batch at a time may lose on a CU share):
+        # the other counts are tried once more with the retuned knobs
+        if moved and args.inflight == 0:
+            best = (n_flight, last)
+            for cand in INFLIGHT_CANDIDATES:
+                if cand in (1, n_flight):
+                    continue
+                rate = timed_inflight(args, R, torch, ctx, desc, batch, budget, arena_inflight(fp), ref,
+                                      total_steps, cand, steps=4 * cand, warmup=cand, verify=False,
+                                      quiet=True)["value"]
+                print("bench: trial %d in flight, retuned knobs: %.3e steps/s" % (cand, rate), flush=True)
+                if rate > best[1] / 0.97:
+                    best = (cand, rate)
+            n_flight = best[0]
     if tuned is not None and cached is None and args.inflight == 0:
         tune_cache.put(cache_key, {"autotune": tuned, "inflight": n_flight,
                                    "inflight_first_pass": int(ctx.get(R.RASP_OPT_FIRST_PASS)),

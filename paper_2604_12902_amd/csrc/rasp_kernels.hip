@@ -22,6 +22,8 @@
 
 #include "rasp_internal.h"
 
+#include <type_traits>
+
 namespace rasp {
 
 // ---------------------------------------------------------------------------
@@ -603,32 +605,38 @@ __device__ __forceinline__ int32_t accumulate(uint32_t op, int32_t a, int32_t d,
     return static_cast<int32_t>(na);
 }
 
-// The hot-cell step loop.  The active lanes of the wave take their
-// transitions together, at most L of them (L wave-uniform, counted in a
+// The lockstep step loop, for a machine's memory in a hot-cell table
+// (HotMem) or wholly in HBM (GlobalMem).  The active lanes of the wave take
+// their transitions together, at most L of them (L wave-uniform, counted in a
 // scalar register).  A lane's transition is common when
 //   * its opcode is LOAD, ADD, SUB/MUL, STORE, the conditional jump, JMP
 //     (classic set) or PRINT with the output full -- not HALT, READ, an
 //     unknown opcode or an append;
 //   * it is not a jump onto its own instruction (i' = i);
-//   * the next instruction's cell and, for ADD, SUB/MUL and STORE, the data
-//     cell are in the table (their tags match);
-//   * the next instruction sits at an even position whose operand follows it
-//     without wrapping, and (n not a power of two) i is not within 4 of the
-//     largest word.
+//   * (n not a power of two) neither i nor a jump target is within 4 of the
+//     largest word (where i + 2 or the next operand's position i' + 1 wraps);
+//   * (hot-cell table) the next instruction's cell and, for ADD, SUB/MUL and
+//     STORE, the data cell are in the table (their tags match), and the next
+//     instruction sits at an even position whose operand follows it without
+//     wrapping.
 // An operand outside [0, n) that a lane uses as its data position or jump
 // target is reduced to its Euclidean remainder first (one wave-uniform test;
 // a multiply-high by a per-machine reciprocal, no division).
 // The inner loop takes common transitions while every lane has one: the
-// straight LDS step, with no test for a fixed point (none is common).  At a
-// transition that is not common for some lane, the outer loop tests every
-// lane for a fixed point exactly (stopping there if any lane sits on one) and
-// takes that one transition with general positions and per-access lookups,
-// as the general step loop does.  Returns the transitions taken, the same for
+// straight step (table: LDS reads, HBM: the store or data load and the next
+// instruction's cell in one 8-byte load), with no test for a fixed point
+// (none is common) and no per-lane loop exit.  At a transition that is not
+// common for some lane, the outer loop tests every lane for a fixed point
+// exactly (stopping there if any lane sits on one) and takes that one
+// transition with general positions and the memory's general accesses, as
+// the general step loop does.  Returns the transitions taken, the same for
 // every active lane; `halted` says whether the lane now sits on a fixed point.
-template <int ISA, bool POW2, bool WM>
-__device__ __forceinline__ uint32_t run_hot(const HotMem &mem, const TapeG &tape, const OutG &out, Regs &r,
-                                            uint32_t L, bool &halted, uint32_t ws)
+template <int ISA, bool POW2, bool WM, class Mem, class Tape>
+__device__ __forceinline__ uint32_t run_lockstep(const Mem &mem, const Tape &tape, const OutG &out, Regs &r,
+                                                 uint32_t L, bool &halted, uint32_t ws)
 {
+    constexpr bool kTable = std::is_same<Mem, HotMem>::value;
+    constexpr bool kHbm = std::is_same<Mem, GlobalMem>::value;
     // bit k: opcode k is common (opcodes above 31 are taken as 31); a memory
     // of fewer than two words has no common transition
     constexpr uint32_t kCommon = ISA == 1 ? 0x1beu : 0xbeu;
@@ -642,8 +650,15 @@ __device__ __forceinline__ uint32_t run_hot(const HotMem &mem, const TapeG &tape
     }
     uint32_t p = r.p, u0 = r.u0, y0 = r.y0;
     int32_t i = r.i, a = r.a;
-    int32_t o = mem.ld(p);
-    int32_t j = mem.ld(POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax));
+    const uint32_t q0 = POW2 ? ((p + 1u) & nm) : operand_pos(i, p, n, imax);
+    static_assert(kTable || kHbm, "a hot-cell table or HBM");
+    int32_t o, j;
+    if constexpr (kHbm) {
+        fetch_pair(mem.M, p, q0, o, j);
+    } else {
+        o = mem.ld(p);
+        j = mem.ld(q0);
+    }
     uint32_t k = 0;
     for (;;) {
         // PRINT is common while the output is full
@@ -682,31 +697,49 @@ __device__ __forceinline__ uint32_t run_hot(const HotMem &mem, const TapeG &tape
             const uint32_t np1 = np + 1u;
             const uint32_t opc = min(op, 31u);
             const uint32_t jx = uses ? jm : np;
-            const uint32_t cf = np >> 1, cd = jx >> 1;
-            const uint32_t sf = mem.slot(cf), sd = mem.slot(cd);
-            const uint32_t dwi = mem.word(sd, jx & 1u);
-            const int2 ef = mem.pair(sf);
-            const int32_t dv = rasp_lds[dwi];
-            const uint32_t tf = mem.tag(sf), td = mem.tag(sd);
-            // the four reads issue together (one LDS round trip a step): the
-            // slot reads are not left behind the test of the tags
-            __builtin_amdgcn_sched_barrier(0);
-            // each condition's lane mask, ORed in scalar registers
-            const uint32_t bad = (tf ^ cf) | (td ^ cd) | (np & 1u) | ((coldops >> opc) & 1u);
-            uint64_t cold = __builtin_amdgcn_ballot_w64(bad != 0u) | __builtin_amdgcn_ballot_w64(ni == i);
-            if (!POW2) {
-                cold |= __builtin_amdgcn_ballot_w64(np1 == n) | __builtin_amdgcn_ballot_w64(i >= imax - 3);
-                if (WM) cold |= __builtin_amdgcn_ballot_w64(taken & (j >= imax - 3));
-            }
-            if (__builtin_expect(cold != 0, 0)) break;
-            // every cell hit: a store into the next instruction's words is
-            // seen by its fetch (equal positions are the same LDS word)
-            const bool st = op == 4u;
-            if (st) rasp_lds[dwi] = a;
             const int32_t jcur = j;
-            o = (st & (jx == np)) ? a : ef.x;
-            j = (st & (jx == np1)) ? a : ef.y;
-            a = accumulate<ISA, WM>(op, a, dv, jcur, ws);
+            if constexpr (kTable) {
+                const uint32_t cf = np >> 1, cd = jx >> 1;
+                const uint32_t sf = mem.slot(cf), sd = mem.slot(cd);
+                const uint32_t dwi = mem.word(sd, jx & 1u);
+                const int2 ef = mem.pair(sf);
+                const int32_t dv = rasp_lds[dwi];
+                const uint32_t tf = mem.tag(sf), td = mem.tag(sd);
+                // the four reads issue together (one LDS round trip a step):
+                // the slot reads are not left behind the test of the tags
+                __builtin_amdgcn_sched_barrier(0);
+                // each condition's lane mask, ORed in scalar registers
+                const uint32_t bad = (tf ^ cf) | (td ^ cd) | (np & 1u) | ((coldops >> opc) & 1u);
+                uint64_t cold = __builtin_amdgcn_ballot_w64(bad != 0u) | __builtin_amdgcn_ballot_w64(ni == i);
+                if (!POW2) {
+                    cold |= __builtin_amdgcn_ballot_w64(np1 == n) | __builtin_amdgcn_ballot_w64(i >= imax - 3);
+                    cold |= __builtin_amdgcn_ballot_w64(taken & (j >= imax - 3));
+                }
+                if (__builtin_expect(cold != 0, 0)) break;
+                // every cell hit: a store into the next instruction's words is
+                // seen by its fetch (equal positions are the same LDS word)
+                const bool st = op == 4u;
+                if (st) rasp_lds[dwi] = a;
+                o = (st & (jx == np)) ? a : ef.x;
+                j = (st & (jx == np1)) ? a : ef.y;
+                a = accumulate<ISA, WM>(op, a, dv, jcur, ws);
+            } else {
+                uint64_t cold = __builtin_amdgcn_ballot_w64(((coldops >> opc) & 1u) != 0u) |
+                                __builtin_amdgcn_ballot_w64(ni == i);
+                if (!POW2) {
+                    cold |= __builtin_amdgcn_ballot_w64(i >= imax - 3);
+                    cold |= __builtin_amdgcn_ballot_w64(taken & (j >= imax - 3));
+                }
+                if (__builtin_expect(cold != 0, 0)) break;
+                const uint32_t nq = POW2 ? (np1 & nm) : (np1 == n ? 0u : np1);
+                // program order: the store, the data word, the next
+                // instruction's words (a store into them is seen by the fetch)
+                if (op == 4u) mem.M[jx] = a;
+                int32_t d = 0;
+                if ((op - 2u) < 2u) d = mem.M[jx];           // ADD, SUB/MUL
+                fetch_pair(mem.M, np, nq, o, j);
+                a = accumulate<ISA, WM>(op, a, d, jcur, ws);
+            }
             i = ni;
             p = np;
         }
@@ -1277,12 +1310,23 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
     uint32_t done = 0, limit = 0, ws = 0, gid = 0;
     const DevBatch *bp = nullptr;
     uint64_t v = 0;
+    // memory in HBM: the lanes step in lockstep, a run stopping when any of
+    // them reaches a fixed point or its budget; idle lanes are refilled once
+    // an epoch (transitions since the last refill, wave-uniform) or when no
+    // lane runs.  Slots: each lane runs up to an epoch on its own, and the
+    // wave refills after every run.
+    uint32_t spent = 0;
 
     for (;;) {
         // ---- refill idle lanes from the queue ----
         const uint64_t idle = __ballot(!has);
         bool claimed = false;
-        if (idle != 0 && !exhausted) {
+        bool due = true;
+        if (MODE == 0) {
+            due = spent >= epoch || idle == ~0ull;
+            if (due) spent = 0;
+        }
+        if (due && idle != 0 && !exhausted) {
             const int leader = __ffsll(static_cast<unsigned long long>(idle)) - 1;
             const uint32_t cnt = __popcll(idle);
             unsigned long long base = 0;
@@ -1391,11 +1435,12 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
         }
         // ---- run ----
         bool finish = false, survive = false;
+        const uint32_t L = MODE == 0 ? wave_min(has ? min(limit - done, epoch - spent) : ~0u) : 0u;
+        uint32_t t = 0;
         if (has) {
             uint32_t lim = limit - done;
             if (lim > epoch) lim = epoch;
             bool halted;
-            uint32_t t;
             // wm is uniform: one of the two loop bodies runs
 #define RASP_RUN(mm, tp, ou)                                                                    \
     (wm ? run_machine<ISA, POW2, true>(mm, tp, r, ou, lim, halted, ws)                         \
@@ -1420,7 +1465,8 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
                 GlobalMem mm{gptr(M)};
                 TapeG tg{gptr(T)};
                 OutG og{gptr(Y)};
-                t = RASP_RUN(mm, tg, og);
+                t = wm ? run_lockstep<ISA, POW2, true>(mm, tg, og, r, L, halted, ws)
+                       : run_lockstep<ISA, POW2, false>(mm, tg, og, r, L, halted, 0u);
             }
 #undef RASP_RUN
             done += t;
@@ -1434,6 +1480,7 @@ __device__ __forceinline__ void persistent_body(const BatchTable *__restrict__ t
                 survive = cut && !halted;
             }
         }
+        if (MODE == 0) spent += wave_max(t);
         // ---- write back the slots of finished machines ----
         // a machine that ran a step (or is new) may have stored: each such
         // lane writes its own slot back, four words (16 bytes) at a time
@@ -1620,8 +1667,8 @@ __device__ __forceinline__ void persistent_hot_body(const BatchTable *__restrict
             const HotMem mm{wave_base + 2u * lane, tag_base + lane, c, mask, gptr(M)};
             const TapeG tg{gptr(T)};
             const OutG og{gptr(Y)};
-            t = wm ? run_hot<ISA, POW2, true>(mm, tg, og, r, L, halted, ws)
-                   : run_hot<ISA, POW2, false>(mm, tg, og, r, L, halted, 0u);
+            t = wm ? run_lockstep<ISA, POW2, true>(mm, tg, og, r, L, halted, ws)
+                   : run_lockstep<ISA, POW2, false>(mm, tg, og, r, L, halted, 0u);
             done += t;
             if (halted || done == limit) {
                 if (done) {

@@ -124,7 +124,8 @@ def _hand_cases():
         return json.load(f)["cases"]
 
 
-@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "hot8-tiny-epoch"])
+@pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "persistent-lds32", "persistent-lds16-split",
+                                   "hot8-tiny-epoch"])
 def test_hand_traced_machines(ctx, rasp, sched):
     configure(ctx, rasp, sched)
     for case in _hand_cases():

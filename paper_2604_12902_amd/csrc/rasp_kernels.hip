@@ -435,6 +435,9 @@ __device__ __forceinline__ bool stuck(uint32_t op, int32_t j, int32_t a, int32_t
 
 // Advance one machine by at most `limit` transitions.  Returns the number
 // applied; `halted` says whether the machine now sits on a fixed point.
+// (The plain kernel and the persistent kernel's slot memories run this loop,
+// each lane leaving it on its own; memory wholly in HBM and hot-cell tables
+// run the lockstep loop below.)
 //
 // Software-pipelined: the words of the next instruction are loaded together
 // with the data word of the current one (after the current store, so that a

@@ -309,7 +309,7 @@ def _random_states(b, seed):
     return st
 
 
-@pytest.mark.parametrize("sched", ["plain", "persistent-lds32", "firstpass-lds16-tiny-epoch",
+@pytest.mark.parametrize("sched", ["plain", "persistent-hbm", "persistent-lds32", "firstpass-lds16-tiny-epoch",
                                    "ldsfirst-lds64", "hot8-tiny-epoch"])
 @pytest.mark.parametrize("isa", [0, 1])
 def test_loaded_states_fuzz(ctx, rasp, sched, isa):

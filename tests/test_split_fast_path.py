@@ -64,3 +64,28 @@ def test_common_positions_of_the_other_loops_are_exact():
                 want_np = _emod(j, n) if taken else np.full(j.shape, _emod(i + 2, n))
                 assert (np_[~rare] == want_np).all()
                 assert (nq[~rare] == _emod(want_np + 1, n)).all()
+
+
+def test_lockstep_euclidean_remainder_is_exact():
+    """The lockstep loops reduce an operand outside [0, n) (n not a power of
+    two, 2 <= n <= 2^30) without a division: a negative word is moved up by
+    big = n * ceil(2^31 / n) into [0, 2^32), then r = u - mulhi(u, rinv) * n
+    with rinv = floor((2^32 - 1) / n) is below 2n, and one subtraction of n
+    finishes.  A model of that arithmetic in numpy (uint64 for the products)
+    against the Euclidean remainder, on the int32 edges and random words."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    edges = np.array([0, 1, -1, 2, -2, 2 ** 31 - 1, -2 ** 31, 2 ** 31 - 2, -2 ** 31 + 1], np.int64)
+    ns = np.concatenate([np.arange(2, 300), rng.integers(2, 2 ** 30 + 1, 300),
+                         [3, 641, 1000, 2 ** 30 - 1, 2 ** 30, 2 ** 29 + 3]]).astype(np.int64)
+    words = np.concatenate([edges, rng.integers(-2 ** 31, 2 ** 31, 2000)])
+    for n in ns:
+        rinv = np.uint64((2 ** 32 - 1) // int(n))
+        big = np.uint64(((2 ** 31 + int(n) - 1) // int(n)) * int(n))
+        assert big < 2 ** 32
+        u = (words & 0xFFFFFFFF).astype(np.uint64) + np.where(words < 0, big, np.uint64(0))
+        u &= np.uint64(0xFFFFFFFF)
+        q = (u * rinv) >> np.uint64(32)
+        rr = u - q * np.uint64(n)
+        assert (rr < 2 * n).all()
+        got = np.where(rr >= np.uint64(n), rr - np.uint64(n), rr)
+        assert (got.astype(np.int64) == _emod(words, n)).all(), n

@@ -795,6 +795,25 @@ __device__ __forceinline__ uint32_t run_lockstep(const Mem &mem, const Tape &tap
         const int32_t jcur = j;
         mem.step(jj, w, st_en, need, np, nq, d, o, j);
         __asm__ volatile("" : : "v"(w));                  // as in the general loop
+        if constexpr (kTable) {
+            // a cell missed here whose slot is empty enters the table (its
+            // two words from HBM, which holds every cell outside the table,
+            // this transition's store included): the next instruction's
+            // cell, else the data cell of a lane that used it
+            const uint32_t xf = np >> 1, xd = jj >> 1;
+            const uint32_t sf = mem.slot(xf), sd = mem.slot(xd);
+            const bool ef = mem.tag(sf) == 0xffffu;
+            const bool ed = (st_en | need) & (xd != xf) & (sd != sf) & (mem.tag(sd) == 0xffffu);
+            if (__builtin_expect(any_lane(ef | ed), 0)) {
+                const uint32_t x = ef ? xf : xd, sl = ef ? sf : sd;
+                if (ef | ed) {
+                    const uint64_t e = *reinterpret_cast<const gu64 *>(mem.M + 2u * x);
+                    mem.put(sl, 0u, static_cast<int32_t>(static_cast<uint32_t>(e)));
+                    mem.put(sl, 1u, static_cast<int32_t>(e >> 32));
+                    reinterpret_cast<uint16_t *>(rasp_lds)[mem.tb + 64u * sl] = static_cast<uint16_t>(x);
+                }
+            }
+        }
         out.st(y0, d, app);
         u0 += rd_ok ? 1u : 0u;
         y0 += app ? 1u : 0u;

@@ -371,8 +371,9 @@ int rasp_free_batch(rasp_ctx *ctx, rasp_batch b);
  *                          cells each machine touches in its last
  *                          RASP_OPT_PROFILE_STEPS transitions, and the persistent
  *                          kernel keeps a machine's profiled cells (up to S,
- *                          hashed into S slots) in LDS, every other word in HBM
- *                          (replaces RASP_OPT_LDS_WORDS for that launch)
+ *                          hashed into S slots) in LDS, every other word in HBM;
+ *                          a cell missed later whose slot is empty joins the
+ *                          table (replaces RASP_OPT_LDS_WORDS for that launch)
  *   RASP_OPT_PROFILE_STEPS transitions profiled at the end of a hot-cell first
  *                          pass, >= 1 (default 256)
  *   RASP_OPT_MISFIT_WAVES  resident waves per compute unit of the launch that

@@ -333,9 +333,11 @@ struct ProfMem {
 // A machine's hot cells in its lane's LDS table, every other word in HBM.
 // Slot s of lane l: its two words at word wb + 128 s (wb = wave base + 2 l),
 // its cell tag (uint16, 0xffff: empty) at halfword tb + 64 s (tb = tag
-// base + l): the 64 lanes of a wave read one slot each without bank
-// conflicts whatever slots they pick.  The LDS copy of a tagged cell is the
-// machine's word; HBM holds it again only after the write-back.
+// base + l): the bank a lane reads depends on its lane, not on the slot it
+// picks (the 64 lanes' two-word reads cover 128 consecutive words).  The LDS
+// copy of a tagged cell is the machine's word; HBM holds it again only after
+// the write-back.  The table starts with the machine's profiled cells; a
+// cell missed later whose slot is empty joins it.
 struct HotMem {
     static constexpr bool kLds = false;
     static constexpr bool kColdIO = false;
